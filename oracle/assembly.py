@@ -1,0 +1,197 @@
+"""Oracle assembly of the ghost-FEM system (test infrastructure).
+
+Discrete problem (section 2, eqs. disc_bil_form and disc_rhs), summed over the
+active cells K after snapping:
+
+    a_h(u, v) = sum_K  int_{K cap Omega} grad u . grad v
+                      + int_{K cap Gamma} lambda_K u v - (n . grad u) v - (n . grad v) u
+    l_h(v)    = sum_K  int_{K cap Omega} f v
+                      + int_{K cap Gamma} lambda_K g v - (n . grad v) g
+
+with lambda_K = gamma C(K) (section 5.2).  On one cell, with phi_i the four
+Q1 shape functions and
+
+    S_ij = int_{K cap Omega} grad phi_i . grad phi_j      M_ij = int_{K cap Omega} phi_i phi_j
+    B_ij = int_{K cap Gamma} (n . grad phi_j) phi_i       L_ij = int_{K cap Gamma} phi_i phi_j
+
+the element matrix is A_K = S - B - B^T + lambda_K L.  The data f and g enter
+through their nodal Q1 interpolants (a reading: the paper writes exact
+integrals of f and g), so that F = M f + G g with G_K = lambda_K L - B^T,
+i.e. G_ij = int lambda_K phi_i phi_j - (n . grad phi_i) phi_j.
+
+Global matrices live on the full (N+1)^2 node grid (k = i + j (N+1)); rows and
+columns of nodes that touch no active cell are empty.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.linalg
+import scipy.sparse as sp
+
+from . import geometry as geo
+from .quadrature import polygon_rule, q1_basis, q1_grad, segment_rule
+
+
+def interior_matrices(h):
+    """Exact Q1 stiffness and mass matrices of a full square cell of side h,
+    vertices counter-clockwise.  The stiffness is independent of h in 2D."""
+    S = np.array([[4.0, -1.0, -2.0, -1.0],
+                  [-1.0, 4.0, -1.0, -2.0],
+                  [-2.0, -1.0, 4.0, -1.0],
+                  [-1.0, -2.0, -1.0, 4.0]]) / 6.0
+    M = np.array([[4.0, 2.0, 1.0, 2.0],
+                  [2.0, 4.0, 2.0, 1.0],
+                  [1.0, 2.0, 4.0, 2.0],
+                  [2.0, 1.0, 2.0, 4.0]]) * (h * h / 36.0)
+    return S, M
+
+
+def reference_integrals(polys, segs):
+    """Reference-cell integrals (h = 1) over the polygons and segments:
+    S, M, B, L as in the module docstring and Kn_ij = int (n.grad phi_i)(n.grad phi_j)."""
+    S = np.zeros((4, 4))
+    M = np.zeros((4, 4))
+    B = np.zeros((4, 4))
+    L = np.zeros((4, 4))
+    Kn = np.zeros((4, 4))
+    for poly in polys:
+        pts, w = polygon_rule(poly)
+        phi = q1_basis(pts)
+        gr = q1_grad(pts)
+        S += np.einsum("imk,jmk,m->ij", gr, gr, w)
+        M += np.einsum("im,jm,m->ij", phi, phi, w)
+    for P, Q in segs:
+        d = np.asarray(Q) - np.asarray(P)
+        length = float(np.hypot(d[0], d[1]))
+        if length == 0.0:
+            continue  # degenerate segment: contributes nothing
+        n = np.array([d[1], -d[0]]) / length  # outward: right of P -> Q
+        pts, w = segment_rule(P, Q)
+        phi = q1_basis(pts)
+        dn = q1_grad(pts) @ n  # (4, m)
+        B += np.einsum("jm,im,m->ij", dn, phi, w)
+        L += np.einsum("im,jm,m->ij", phi, phi, w)
+        Kn += np.einsum("im,jm,m->ij", dn, dn, w)
+    # the symmetric integrals are symmetric in exact arithmetic; remove the
+    # rounding-order asymmetry of the sums so that A_K = A_K^T exactly
+    sym = lambda X: 0.5 * (X + X.T)  # noqa: E731
+    return sym(S), sym(M), B, sym(L), sym(Kn)
+
+
+def local_eigen_constant(polys, segs):
+    """C(K) h from the local generalised eigenproblem of section 5.2:
+    Kn v = Lambda S v with Kn the boundary normal-derivative matrix and S the
+    cut-cell stiffness.  Both vanish on constants, so the eigenvalue is taken
+    in the rank sense of section 4.4 (restriction to the complement of the
+    constants) and C = max Lambda."""
+    S, _, _, _, Kn = reference_integrals(polys, segs)
+    Q = np.linalg.svd(np.ones((1, 4)))[2][1:].T  # 4x3 basis orthogonal to constants
+    return float(scipy.linalg.eigh(Q.T @ Kn @ Q, Q.T @ S @ Q, eigvals_only=True).max())
+
+
+def cut_element(psi4, h, gamma=2.0, rule=geo.STAB_PAPER, lambda_fixed=0.0):
+    """Element matrices (A_K, M_K, G_K) and (type, C, lambda) of one cut cell."""
+    g = geo.cut_geometry(psi4)
+    t, polys, segs, _ = g
+    S, Mr, B, L, _ = reference_integrals(polys, segs)
+    if rule == geo.STAB_FIXED:
+        C = 0.0
+        lam = lambda_fixed
+    else:
+        C = geo.stabilization_constant(psi4, h, rule, geometry=g)
+        lam = gamma * C
+    lam_ref = lam * h  # lambda_K L_phys = (lambda_K h) L_ref
+    A = S - B - B.T + lam_ref * L
+    G = lam_ref * L - B.T
+    return A, Mr * (h * h), G, (t, C, lam)
+
+
+@dataclass
+class Discretisation:
+    N: int
+    h: float
+    box: tuple
+    psi: np.ndarray        # snapped nodal level set
+    cell_type: np.ndarray  # (N*N,) type codes of geometry
+    cell_lambda: np.ndarray
+    cell_C: np.ndarray
+    A: sp.csr_matrix
+    M: sp.csr_matrix
+    G: sp.csr_matrix
+    active: np.ndarray     # (n,) bool: vertex of an active cell
+
+    @property
+    def n(self):
+        return (self.N + 1) ** 2
+
+    def rhs(self, f, g):
+        """F = M f + G g (nodal interpolants of f and g)."""
+        return self.M @ f + self.G @ g
+
+    @property
+    def cut_cells(self):
+        t = self.cell_type
+        return np.nonzero((t != geo.EXTERNAL) & (t != geo.INTERNAL))[0]
+
+
+def cell_vertex_indices(N):
+    """(N*N, 4) global node indices of v0..v3 of every cell."""
+    ci, cj = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
+    k0 = (ci + cj * (N + 1)).ravel()
+    return np.stack([k0, k0 + 1, k0 + N + 2, k0 + N + 1], axis=1)
+
+
+def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
+             rule=geo.STAB_PAPER, lambda_fixed=0.0, snap=True):
+    """Snap, classify and assemble A, M, G on the full node grid."""
+    h = (box[2] - box[0]) / N
+    psi_s = geo.snap(psi, h, alpha) if snap else np.asarray(psi, dtype=np.float64).copy()
+    psi4 = geo.cell_vertex_values(psi_s, N)
+    ctype = geo.classify(psi4)
+    V = cell_vertex_indices(N)
+    n = (N + 1) ** 2
+
+    rows, cols, aval, mval, gval = [], [], [], [], []
+    S_int, M_int = interior_matrices(h)
+    inner = np.nonzero(ctype == geo.INTERNAL)[0]
+    if len(inner):
+        Vi = V[inner]
+        rows.append(np.repeat(Vi[:, :, None], 4, axis=2).ravel())
+        cols.append(np.repeat(Vi[:, None, :], 4, axis=1).ravel())
+        aval.append(np.broadcast_to(S_int, (len(inner), 4, 4)).ravel())
+        mval.append(np.broadcast_to(M_int, (len(inner), 4, 4)).ravel())
+        gval.append(np.zeros(len(inner) * 16))
+
+    cell_lambda = np.zeros(N * N)
+    cell_C = np.zeros(N * N)
+    cut = np.nonzero((ctype != geo.EXTERNAL) & (ctype != geo.INTERNAL))[0]
+    for c in cut:
+        A_K, M_K, G_K, (_, C, lam) = cut_element(psi4[c], h, gamma, rule, lambda_fixed)
+        cell_lambda[c] = lam
+        cell_C[c] = C
+        v = V[c]
+        rows.append(np.repeat(v, 4))
+        cols.append(np.tile(v, 4))
+        aval.append(A_K.ravel())
+        mval.append(M_K.ravel())
+        gval.append(G_K.ravel())
+
+    if rows:
+        r = np.concatenate(rows)
+        c_ = np.concatenate(cols)
+        A = sp.coo_matrix((np.concatenate(aval), (r, c_)), shape=(n, n)).tocsr()
+        M = sp.coo_matrix((np.concatenate(mval), (r, c_)), shape=(n, n)).tocsr()
+        G = sp.coo_matrix((np.concatenate(gval), (r, c_)), shape=(n, n)).tocsr()
+        # A and M are symmetric in exact arithmetic; make them so in floating
+        # point too (the duplicate summation order may differ between (i,j)
+        # and (j,i))
+        A = ((A + A.T) * 0.5).tocsr()
+        M = ((M + M.T) * 0.5).tocsr()
+    else:
+        A = M = G = sp.csr_matrix((n, n))
+    active = np.zeros(n, dtype=bool)
+    active[V[ctype != geo.EXTERNAL].ravel()] = True
+    return Discretisation(N, h, tuple(box), psi_s, ctype, cell_lambda, cell_C,
+                          A, M, G, active)

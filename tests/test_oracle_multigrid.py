@@ -1,0 +1,149 @@
+"""Pins of the oracle's multigrid (CPU only): the printed restriction matrix,
+exact reproduction of bilinear functions by prolongation, Galerkin nestedness
+of the interior stencil, the Gauss-Seidel phase property, agreement with a
+direct solve, and the paper's convergence-factor statements (section 5.3)."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import assembly as asm
+from oracle import multigrid as mg
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_restriction_matches_printed_n2_matrix():
+    R_paper = np.loadtxt(os.path.join(GOLDEN, "restriction_n2.txt"))
+    R = mg.prolongation(1).T.toarray()
+    np.testing.assert_array_equal(R, R_paper)
+
+
+def test_prolongation_reproduces_bilinear_functions():
+    Nc = 8
+    xc, yc = W.grid_xy(Nc)
+    xf, yf = W.grid_xy(2 * Nc)
+    fun = lambda x, y: 0.3 - 1.7 * x + 2.2 * y + 0.9 * x * y  # noqa: E731
+    np.testing.assert_allclose(mg.prolongation(Nc) @ fun(xc, yc), fun(xf, yf), atol=1e-14)
+
+
+@pytest.fixture(scope="module")
+def flower64():
+    d = asm.assemble(W.flower(64), 64)
+    return d, mg.build_hierarchy(d)
+
+
+def test_galerkin_interior_stencil_is_q1(flower64):
+    """Shape functions are nested, so away from the boundary every Galerkin
+    coarse operator is the Q1 stencil again (8/3 centre, -1/3 neighbours)."""
+    _, H = flower64
+    for lv in H.levels[1:]:
+        N = lv.N
+        k = N // 2 + (N // 2) * (N + 1)
+        if N < 16:
+            continue
+        row = lv.A.getrow(k).toarray().ravel()
+        assert row[k] == pytest.approx(8 / 3, abs=1e-13)
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                if di or dj:
+                    assert row[k + di + dj * (N + 1)] == pytest.approx(-1 / 3, abs=1e-13)
+
+
+def test_hierarchy_shape_and_symmetry(flower64):
+    d, H = flower64
+    assert [lv.N for lv in H.levels] == [64, 32, 16, 8, 4]
+    for lv in H.levels:
+        assert abs(lv.A - lv.A.T).max() <= 1e-14 * abs(lv.A).max()
+        # coarse active set: a node whose 3x3 fine support touches an active node
+    for fine, coarse in zip(H.levels[:-1], H.levels[1:]):
+        touched = (abs(fine.P.T) @ fine.active.astype(float)) > 0
+        np.testing.assert_array_equal(touched, coarse.active)
+        assert np.all(fine.active[fine.cut])
+
+
+def test_colour_phase_zeroes_its_residual(flower64):
+    d, H = flower64
+    lv = H.levels[0]
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(d.n) * lv.active
+    b = rng.standard_normal(d.n) * lv.active
+    for c in range(4):
+        mg._phase(x, b, lv.colour_rows[c], lv.colour_A[c], lv.diag)
+        r = b - lv.A @ x
+        assert np.abs(r[lv.colour_rows[c]]).max() < 1e-12
+
+
+def test_colours_do_not_couple(flower64):
+    _, H = flower64
+    lv = H.levels[1]
+    col = mg.node_colours(lv.N)
+    A = lv.A.tocoo()
+    off = A.row != A.col
+    assert np.all(col[A.row[off]] != col[A.col[off]])
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_multigrid_solution_equals_direct_solve(N):
+    p = W.flower_mms(N)
+    d = asm.assemble(p.psi, N)
+    H = mg.build_hierarchy(d)
+    F = d.rhs(p.f, p.g)
+    res = mg.solve(H, F, tol=1e-13, max_cycles=60)
+    a = np.nonzero(d.active)[0]
+    u = np.zeros(d.n)
+    u[a] = spla.spsolve(d.A[a][:, a].tocsc(), F[a])
+    assert res.converged
+    assert np.abs(res.u - u).max() <= 1e-10 * np.abs(u).max()
+
+
+def test_paper_convergence_statements_circle():
+    """Circle r = 0.4 on [0,1]^2 (section 5.3): without extra smoothing the
+    two-grid factor is far above 0.1; with gamma = 2 and eta = 4 it reaches
+    the optimal ~0.1 (here at or below it); the W-cycle matches the two-grid
+    scheme.  Checked with the four-colour and the lexicographic sweep."""
+    N = 64
+    d = asm.assemble(W.circle_quadratic(N), N, box=W.UNIT_BOX)
+    H2 = mg.two_grid(d)
+    rho0 = mg.rho_protocol(H2, eta=0)
+    rho4 = mg.rho_protocol(H2, eta=4)
+    assert rho0 > 0.2
+    assert rho4 < 0.12
+    assert mg.rho_protocol(H2, eta=4, smoother="lex") < 0.12
+    rhos = [mg.rho_protocol(H2, eta=e) for e in range(5)]
+    assert rhos[-1] < rhos[0]
+    HV = mg.build_hierarchy(d)
+    rhoW = mg.rho_protocol(HV, eta=4, gamma_star=2)
+    assert abs(rhoW - rho4) < 0.03
+
+
+@pytest.mark.parametrize("name", ["paper_flower", "hourglass"])
+def test_paper_convergence_other_geometries(name):
+    """Flower and hourglass of section 5.3 with gamma = 2, eta = 4: two-grid
+    factor ~0.1 (at or below it)."""
+    N = 64
+    psi = W.paper_flower(N) if name == "paper_flower" else W.hourglass(N)
+    d = asm.assemble(psi, N)
+    assert mg.rho_protocol(mg.two_grid(d), eta=4) < 0.12
+
+
+def test_larger_gamma_is_worse():
+    """Larger stabilisation degrades the multigrid (sections 4.4 and 5.3)."""
+    N = 64
+    psi = W.circle_quadratic(N)
+    r2 = mg.rho_protocol(mg.two_grid(asm.assemble(psi, N, box=W.UNIT_BOX, gamma=2.0)), eta=0)
+    r10 = mg.rho_protocol(mg.two_grid(asm.assemble(psi, N, box=W.UNIT_BOX, gamma=10.0)), eta=0)
+    assert r10 > r2
+
+
+def test_warm_start_and_history(flower64):
+    d, H = flower64
+    p = W.flower_mms(64)
+    F = d.rhs(p.f, p.g)
+    res = mg.solve(H, F, tol=1e-10, max_cycles=50)
+    assert res.converged and res.hist[-1] <= 1e-10 * np.abs(F).max()
+    assert res.hist[0] == np.abs(F).max()
+    again = mg.solve(H, F, tol=1e-10, max_cycles=50, u0=res.u)
+    assert again.cycles == 0

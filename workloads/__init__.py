@@ -1,0 +1,183 @@
+"""Seeded synthetic inputs for the ghost-FEM multigrid solver.
+
+This module only *generates inputs*: nodal level-set values, manufactured
+solutions and right-hand sides, and the seeded draws of the batched workload.
+It holds none of the method's arithmetic (no geometry, no quadrature, no
+multigrid), so both the CPU oracle and the HIP path can be fed from it without
+sharing any of the solver's code.
+
+Grid convention: a uniform grid of N x N cells over the box
+[x_lo, x_hi] x [y_lo, y_hi]; node (i, j) sits at (x_lo + i h, y_lo + j h) with
+h = (x_hi - x_lo) / N, and its flat index is k = i + j (N + 1) (the single
+index of the paper's two-dimensional transfer-operator section).
+Arrays are returned as float64 numpy arrays of length (N + 1)**2.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+BOX = (-1.0, -1.0, 1.0, 1.0)
+UNIT_BOX = (0.0, 0.0, 1.0, 1.0)
+
+
+def grid_xy(N: int, box=BOX):
+    """Node coordinates (x, y), each of shape ((N+1)**2,), x-index fastest."""
+    x_lo, y_lo, x_hi, y_hi = box
+    xs = x_lo + (x_hi - x_lo) * np.arange(N + 1, dtype=np.float64) / N
+    ys = y_lo + (y_hi - y_lo) * np.arange(N + 1, dtype=np.float64) / N
+    X, Y = np.meshgrid(xs, ys, indexing="xy")  # X[j, i] = xs[i]
+    return X.ravel(), Y.ravel()
+
+
+# ----------------------------------------------------------------------------
+# Level sets (Omega = {psi < 0})
+# ----------------------------------------------------------------------------
+
+def circle(N, radius=0.5, center=(0.0, 0.0), box=BOX):
+    """Signed distance to a circle: sqrt((x-cx)^2 + (y-cy)^2) - r."""
+    x, y = grid_xy(N, box)
+    return np.sqrt((x - center[0]) ** 2 + (y - center[1]) ** 2) - radius
+
+
+def circle_quadratic(N, radius=0.4, center=(0.5, 0.5), box=UNIT_BOX):
+    """The disk of the paper's 2D tests, as a quadratic level set
+    (x-xc)^2 + (y-yc)^2 - r^2 on [0,1]^2 (section 5.3, circular domain)."""
+    x, y = grid_xy(N, box)
+    return (x - center[0]) ** 2 + (y - center[1]) ** 2 - radius ** 2
+
+
+def flower(N, center=(0.02, 0.03), r0=0.5, amp=0.1, petals=5, box=BOX):
+    """Five-petal flower r - 0.5 - 0.1 sin(5 theta) about (0.02, 0.03)."""
+    x, y = grid_xy(N, box)
+    X = x - center[0]
+    Y = y - center[1]
+    r = np.sqrt(X * X + Y * Y)
+    th = np.arctan2(Y, X)
+    return r - r0 - amp * np.sin(petals * th)
+
+
+def paper_flower(N, box=BOX):
+    """The flower of the paper's 2D tests (section 5.3, flower-shaped domain):
+    R - 0.52 - (Y^5 + 5 X^4 Y - 10 X^2 Y^3) / (5 R^5) about (0.03 sqrt 3, 0.04 sqrt 2)."""
+    x, y = grid_xy(N, box)
+    X = x - 0.03 * math.sqrt(3.0)
+    Y = y - 0.04 * math.sqrt(2.0)
+    R = np.sqrt(X * X + Y * Y)
+    Rs = np.where(R == 0.0, 1.0, R)
+    return R - 0.52 - (Y ** 5 + 5 * X ** 4 * Y - 10 * X ** 2 * Y ** 3) / (5 * Rs ** 5)
+
+
+def hourglass(N, box=BOX):
+    """The hourglass of the paper's 2D tests (section 5.3):
+    256 Y^4 - 16 X^4 - 128 Y^2 + 36 X^2 about (0.03 sqrt 3, 0.04 sqrt 2)."""
+    x, y = grid_xy(N, box)
+    X = x - 0.03 * math.sqrt(3.0)
+    Y = y - 0.04 * math.sqrt(2.0)
+    return 256 * Y ** 4 - 16 * X ** 4 - 128 * Y ** 2 + 36 * X ** 2
+
+
+def ellipse(N, a=0.7, b=0.35, phi=0.3, center=(0.0, 0.0), box=BOX):
+    """Rotated ellipse b (sqrt((x'/a)^2 + (y'/b)^2) - 1), with
+    x' = cos(phi)(x-cx) + sin(phi)(y-cy), y' = -sin(phi)(x-cx) + cos(phi)(y-cy)."""
+    x, y = grid_xy(N, box)
+    dx = x - center[0]
+    dy = y - center[1]
+    xp = math.cos(phi) * dx + math.sin(phi) * dy
+    yp = -math.sin(phi) * dx + math.cos(phi) * dy
+    return b * (np.sqrt((xp / a) ** 2 + (yp / b) ** 2) - 1.0)
+
+
+def vertical_line(N, theta, box=UNIT_BOX):
+    """x - 1 + (1 - theta) h: the rectangle cut by a vertical line (section 5.3)."""
+    x, _ = grid_xy(N, box)
+    h = (box[2] - box[0]) / N
+    return x - 1.0 + (1.0 - theta) * h
+
+
+# ----------------------------------------------------------------------------
+# Manufactured solutions: (u, f = -lap u) evaluated at the nodes
+# ----------------------------------------------------------------------------
+
+def mms_exp_sin(N, box=BOX):
+    """u = exp(x) sin(y); harmonic, so f = 0."""
+    x, y = grid_xy(N, box)
+    u = np.exp(x) * np.sin(y)
+    return u, np.zeros_like(u)
+
+
+def mms_flower(N, box=BOX):
+    """u = sin(pi x) cos(pi y) + x^2; f = -lap u = 2 pi^2 sin(pi x) cos(pi y) - 2."""
+    x, y = grid_xy(N, box)
+    s = np.sin(np.pi * x) * np.cos(np.pi * y)
+    return s + x * x, 2.0 * np.pi ** 2 * s - 2.0
+
+
+def adjoint_target(N, box=BOX):
+    """u_t = cos(2 pi x) sin(pi y) (the misfit target of the adjoint workload)."""
+    x, y = grid_xy(N, box)
+    return np.cos(2 * np.pi * x) * np.sin(np.pi * y)
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Problem:
+    name: str
+    N: int
+    psi: np.ndarray
+    f: np.ndarray
+    g: np.ndarray
+    u_exact: np.ndarray | None = None
+    box: tuple = BOX
+    meta: dict = field(default_factory=dict)
+
+
+def circle_mms(N=64):
+    """Circle r = 0.5, u = exp(x) sin(y), g = u at the nodes."""
+    u, f = mms_exp_sin(N)
+    return Problem("circle_mms", N, circle(N), f, u.copy(), u)
+
+
+def flower_mms(N=1024):
+    """Flower r - 0.5 - 0.1 sin(5 theta) about (0.02, 0.03), u = sin(pi x) cos(pi y) + x^2."""
+    u, f = mms_flower(N)
+    return Problem("flower_mms", N, flower(N), f, u.copy(), u)
+
+
+def ellipse_mms(N=4096):
+    """Ellipse (0.7, 0.35) rotated 0.3 rad, the flower's manufactured solution."""
+    u, f = mms_flower(N)
+    return Problem("ellipse_mms", N, ellipse(N), f, u.copy(), u)
+
+
+def batched_draws(count=256, seed=0, sizes=(64, 128, 256, 512)):
+    """Seeded random-ellipse problems of the batched workload.
+
+    Draw order per problem (numpy default_rng(seed)): N from `sizes`,
+    semi-axes a, b ~ U[0.2, 0.8], rotation ~ U[0, pi], centre ~ U[-0.1, 0.1]^2,
+    then f ~ U[-1, 1] per node; g = 0.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for p in range(count):
+        N = int(rng.choice(np.asarray(sizes)))
+        a = float(rng.uniform(0.2, 0.8))
+        b = float(rng.uniform(0.2, 0.8))
+        phi = float(rng.uniform(0.0, math.pi))
+        cx, cy = (float(v) for v in rng.uniform(-0.1, 0.1, size=2))
+        psi = ellipse(N, a=a, b=b, phi=phi, center=(cx, cy))
+        f = rng.uniform(-1.0, 1.0, size=(N + 1) ** 2)
+        out.append(Problem(f"ellipse_{p}", N, psi, f, np.zeros_like(f), None,
+                           meta=dict(a=a, b=b, phi=phi, cx=cx, cy=cy)))
+    return out
+
+
+def random_directions(n, count, seed=1):
+    """Seeded standard-normal directions (count x n) for finite-difference checks."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((count, n))
