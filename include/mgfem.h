@@ -1,0 +1,230 @@
+/*
+ * mgfem.h -- C ABI of the MI355X (gfx950) multigrid solver for the nodal
+ * ghost finite-element discretisation of the Poisson problem on a domain
+ * given by a level set (Dilip & Coco, "Multigrid methods for the ghost finite
+ * element approximation of elliptic problems", arXiv 2505.05105).
+ *
+ * Problem (section 2): -lap u = f in Omega = {psi < 0}, u = g on its boundary,
+ * discretised with Q1 elements on the active cells of a uniform N x N grid
+ * over a box, Dirichlet data imposed weakly by Nitsche's method (eqs.
+ * disc_bil_form, disc_rhs) with the cell-wise stabilisation
+ * lambda_K = gamma C(K) (section 5.2), after snapping back to grid (section 2).
+ * Solver (sections 3 and 5): Gauss-Seidel smoothing in four colours plus eta
+ * extra sweeps on the vertices of cut cells, restriction by the transposed
+ * bilinear prolongation, Galerkin coarse operators R A P, exact solve on the
+ * coarsest grid, V- or W-cycles.
+ *
+ * Conventions shared by every call:
+ *  - Grid arrays are float64 arrays in device memory of length (N+1)^2; node
+ *    (i, j) at (x_lo + i h, y_lo + j h), h = (x_hi - x_lo)/N, has flat index
+ *    k = i + j (N+1) (the single index of section 5.1).  Cell (i, j) has flat
+ *    index i + j N.
+ *  - The caller owns every array it passes; the library never frees or keeps
+ *    a caller pointer after a call returns.  The library owns the handle and
+ *    all of its workspace (hierarchy, stencils, lists).
+ *  - Work is enqueued on the stream given to setup (a hipStream_t passed as
+ *    void*; NULL is the default stream).  Calls that return host results
+ *    synchronise that stream before they return.
+ *  - Every call returns an mgfem_status code and never throws.  On an error
+ *    the outputs are unspecified, except MGFEM_ERR_NOT_CONVERGED: then u and
+ *    the residual history are valid for the cycles that were run.
+ *  - Nodes that are not vertices of an active cell ("inactive") hold 0 in
+ *    every output array.
+ *  - A handle may be used by one host thread at a time.
+ */
+#ifndef MGFEM_H
+#define MGFEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgfem_ctx* mgfem_handle;
+
+enum mgfem_status {
+  MGFEM_OK = 0,
+  MGFEM_ERR_INVALID_ARG = 1,     /* bad size, pointer or parameter */
+  MGFEM_ERR_OOM = 2,             /* device allocation failed */
+  MGFEM_ERR_HIP = 3,             /* a HIP runtime call failed */
+  MGFEM_ERR_NOT_CONVERGED = 4,   /* max_cycles reached above the tolerance */
+  MGFEM_ERR_DIVERGED = 5,        /* non-finite residual, or growth over 3 cycles */
+  MGFEM_ERR_SINGULAR_COARSE = 6, /* non-positive pivot in the coarsest Cholesky */
+  MGFEM_ERR_EMPTY_DOMAIN = 7,    /* no node with psi < 0 after snapping */
+  MGFEM_ERR_UNSUPPORTED = 8      /* option not available in this build */
+};
+
+/* Stabilisation rule for lambda_K = gamma C(K) (section 5.2). */
+enum mgfem_stab {
+  MGFEM_STAB_PAPER = 0,     /* closed forms: eq. c_triangle, the quadrilateral
+                               formula, eq. c_pentagon for pentagons */
+  MGFEM_STAB_LOCAL_EIG = 1, /* max eigenvalue of the local 4x4 generalised
+                               eigenproblem of section 5.2 */
+  MGFEM_STAB_FIXED = 2      /* lambda_K = lambda_fixed on every cut cell */
+};
+
+enum mgfem_precision {
+  MGFEM_PREC_FP64 = 0,  /* every cycle in float64 */
+  MGFEM_PREC_MIXED = 1  /* float32 cycles inside float64 defect correction;
+                           float64 outer residual, geometry and coarsest solve */
+};
+
+enum mgfem_cycle { MGFEM_CYCLE_V = 1, MGFEM_CYCLE_W = 2 }; /* gamma* of section 3.2 */
+
+#define MGFEM_SOLVE_WARM_START 1u /* start from the u passed in, not from 0 */
+
+typedef struct {
+  int32_t stab_rule;    /* enum mgfem_stab, default MGFEM_STAB_PAPER */
+  double gamma;         /* lambda_K = gamma C(K); must exceed 1 (section 4.4); default 2 */
+  double lambda_fixed;  /* used by MGFEM_STAB_FIXED only */
+  double snap_alpha;    /* snapping threshold h^alpha (section 2); default 1.75 */
+  int32_t nu1, nu2;     /* pre/post smoothing steps; default 2, 1 */
+  int32_t eta;          /* extra cut-cell sweeps per smoothing step; default 4 */
+  int32_t coarsest_n;   /* cells per side of the coarsest grid; default 4 */
+  int32_t precision;    /* enum mgfem_precision, default MGFEM_PREC_FP64 */
+  int32_t cycle;        /* enum mgfem_cycle, default MGFEM_CYCLE_V */
+  double x_lo, y_lo, x_hi, y_hi; /* square box; default [-1, 1]^2 */
+} mgfem_params;
+
+typedef struct {
+  int32_t N;                 /* cells per side of the finest grid */
+  int32_t n_levels;          /* grids in the hierarchy, finest to coarsest */
+  int64_t n_active;          /* active fine nodes (degrees of freedom) */
+  int64_t n_cells_by_type[7];/* external, triangle, quadrilateral, pentagon,
+                                internal, saddle split, saddle hexagon */
+  int64_t n_snapped;         /* nodes whose psi was set to 0 by snapping */
+  int64_t n_cut_vertices;    /* fine nodes in the extra-smoothing set */
+  int32_t coarse_n;          /* unknowns of the coarsest exact solve */
+  double min_theta;          /* smallest cut fraction on a cut edge */
+  double max_lambda;         /* largest lambda_K */
+  double setup_ms;           /* device time of the last setup */
+} mgfem_info;
+
+/* Fill *p with the defaults listed above. */
+int mgfem_default_params(mgfem_params* p);
+
+/*
+ * Build the solver for one level set.
+ *  psi_dev : device, (N+1)^2 float64 nodal values of psi (read only).
+ *  N       : cells per side; must be coarsest_n times a power of two, >= 2 coarsest_n.
+ *  p       : parameters (NULL for the defaults).
+ *  stream  : hipStream_t as void* (NULL = default stream).
+ *  out     : receives the handle; release it with mgfem_destroy.
+ * Runs snapping, cell classification and cut geometry, C(K) and lambda_K,
+ * the fine stencils of A, M and G, the Galerkin hierarchy, the cut-vertex
+ * lists and the coarsest Cholesky factor, all on the device.
+ * Errors: INVALID_ARG, OOM, HIP, EMPTY_DOMAIN, SINGULAR_COARSE.
+ */
+int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* p, void* stream,
+                mgfem_handle* out);
+
+/*
+ * Solve A u = F with F = M f + G g (Q1 interpolants of f and g; F follows
+ * eq. disc_rhs) by repeated cycles until ||F - A u||_inf <= rel_tol ||F||_inf.
+ *  f_dev, g_dev  : device (N+1)^2 float64 nodal source and Dirichlet data
+ *                  (g is read on the vertices of cut cells only).
+ *  rel_tol       : relative l-infinity residual tolerance (0 or less: run
+ *                  exactly max_cycles cycles).
+ *  max_cycles    : >= 0.
+ *  flags         : MGFEM_SOLVE_WARM_START to start from the incoming u_dev.
+ *  u_dev         : device (N+1)^2 float64, receives the solution.
+ *  res_hist_host : host, max_cycles+1 float64 or NULL; entry m receives
+ *                  ||F - A u_m||_inf (entry 0 for the start), section 3.1.
+ *  n_cycles      : host, receives the number of cycles run (may be NULL).
+ * In mixed precision one cycle is one float64 outer defect-correction step
+ * around one float32 cycle.  Returns OK, NOT_CONVERGED, DIVERGED or an error.
+ */
+int mgfem_solve(mgfem_handle h, const double* f_dev, const double* g_dev, double rel_tol,
+                int32_t max_cycles, uint32_t flags, double* u_dev, double* res_hist_host,
+                int32_t* n_cycles);
+
+/*
+ * Adjoint of the solve: lam = B_k^T dJ/du with B_k the map F -> u of k cycles,
+ * run as k transposed cycles from zero (every smoothing phase in reverse
+ * order, nu1 and nu2 swapped); k is fixed by rel_tol/max_cycles as in
+ * mgfem_solve.  Then dJ/df = M lam and dJ/dg = G^T lam.
+ *  dJdu_dev  : device (N+1)^2 float64.
+ *  lam_dev   : device (N+1)^2 float64 or NULL.
+ *  dJdf_dev, dJdg_dev : device (N+1)^2 float64 or NULL.
+ *  res_hist_host, n_cycles : as in mgfem_solve (history of the adjoint system).
+ * Always runs in float64.
+ */
+int mgfem_adjoint(mgfem_handle h, const double* dJdu_dev, double rel_tol, int32_t max_cycles,
+                  double* lam_dev, double* dJdf_dev, double* dJdg_dev, double* res_hist_host,
+                  int32_t* n_cycles);
+
+/*
+ * Misfit J = 1/2 (u - u_t)^T M (u - u_t) (nodal interpolants) and
+ * dJ/du = M (u - u_t).  J_host: host scalar; dJdu_dev: device (N+1)^2 or NULL.
+ */
+int mgfem_misfit(mgfem_handle h, const double* u_dev, const double* ut_dev, double* J_host,
+                 double* dJdu_dev);
+
+/* Counts and extrema of the setup (fills *info). */
+int mgfem_query(mgfem_handle h, mgfem_info* info);
+
+/* What mgfem_export copies out. */
+enum mgfem_export_what {
+  MGFEM_EXPORT_PSI = 0,        /* snapped psi, (N+1)^2 float64 (level 0 only) */
+  MGFEM_EXPORT_CELL_TYPE = 1,  /* cell type codes as float64, N^2 (level 0 only) */
+  MGFEM_EXPORT_CELL_LAMBDA = 2,/* lambda_K per cell (0 off cut cells), N^2 float64 */
+  MGFEM_EXPORT_A = 3,          /* 9 stencil planes of A_l, 9 (N_l+1)^2 float64;
+                                  plane p = (di+1) + 3 (dj+1) holds the coefficient
+                                  of node (i+di, j+dj) in row (i, j) */
+  MGFEM_EXPORT_M = 4,          /* 9 planes of the mass matrix (level 0 only) */
+  MGFEM_EXPORT_G = 5,          /* 9 planes of the boundary-load matrix G (level 0 only) */
+  MGFEM_EXPORT_NODE_FLAGS = 6, /* per node, as float64: bit 0 active, bit 1 stored
+                                  stencil, bit 2 extra-smoothing vertex */
+  MGFEM_EXPORT_RHS = 7         /* F of the last solve, (N+1)^2 float64 */
+};
+
+/* Copy an internal array of level `level` into device memory dst_dev
+ * (sizes as listed above).  For inspection and tests; synchronises. */
+int mgfem_export(mgfem_handle h, int32_t what, int32_t level, double* dst_dev);
+
+/* Grid size N_l of level `level` (0 = finest), or -1 if out of range. */
+int32_t mgfem_level_n(mgfem_handle h, int32_t level);
+
+/*
+ * Apply `steps` smoothing steps of level `level` to x_dev for the right-hand
+ * side b_dev (both device, (N_l+1)^2 float64; x is updated in place).
+ * reverse != 0 applies the transposed step.  For tests of single sweeps.
+ */
+int mgfem_smooth(mgfem_handle h, int32_t level, double* x_dev, const double* b_dev,
+                 int32_t steps, int32_t reverse);
+
+/* Release the handle and all of its device memory. */
+int mgfem_destroy(mgfem_handle h);
+
+/* Static text for a status code. */
+const char* mgfem_status_string(int code);
+
+/* Text of the last error on h (thread-local last setup error when h is NULL). */
+const char* mgfem_last_error(mgfem_handle h);
+
+/*
+ * Batched form: `count` independent problems (different psi and N) solved
+ * together.  Setup builds every hierarchy; the solve runs all problems'
+ * cycles in one persistent cooperative launch per solve, with per-problem
+ * convergence.  Parameters are shared by all problems.
+ *  psi_dev[i] : device (N[i]+1)^2 float64.  N[i] as in mgfem_setup.
+ */
+int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32_t* N,
+                        const mgfem_params* p, void* stream, mgfem_handle* out);
+
+/*
+ *  f_dev[i], g_dev[i], u_dev[i] : device (N[i]+1)^2 float64.
+ *  res_hist_host : host count*(max_cycles+1) float64 or NULL (row i for problem i).
+ *  n_cycles      : host count int32 or NULL.
+ * Returns OK when every problem converged, NOT_CONVERGED otherwise.
+ */
+int mgfem_solve_batched(mgfem_handle h, const double* const* f_dev, const double* const* g_dev,
+                        double rel_tol, int32_t max_cycles, double* const* u_dev,
+                        double* res_hist_host, int32_t* n_cycles);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGFEM_H */

@@ -1,0 +1,418 @@
+// C ABI of the library: argument checks, the hierarchy's allocation, the
+// solve / adjoint drivers and their convergence bookkeeping.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "mgfem_internal.h"
+
+using namespace mgfem;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+int fail(mgfem_ctx* c, int code, const std::string& msg) {
+  if (c) c->last_error = msg;
+  else g_setup_error = msg;
+  return code;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int check_params(const mgfem_params& p, int N, std::string& why) {
+  if (p.stab_rule < 0 || p.stab_rule > 2) return why = "stab_rule", 1;
+  if (p.stab_rule != MGFEM_STAB_FIXED && !(p.gamma > 1.0))
+    return why = "gamma must exceed 1 (coercivity, section 4.4)", 1;
+  if (p.stab_rule == MGFEM_STAB_FIXED && !(p.lambda_fixed > 0.0)) return why = "lambda_fixed", 1;
+  if (!(p.snap_alpha > 0.0)) return why = "snap_alpha", 1;
+  if (p.nu1 < 0 || p.nu2 < 0 || p.nu1 + p.nu2 == 0 || p.eta < 0 || p.nu1 > 64 || p.nu2 > 64 || p.eta > 64)
+    return why = "nu1/nu2/eta", 1;
+  if (p.coarsest_n < 1 || p.coarsest_n > 16) return why = "coarsest_n must be in [1, 16]", 1;
+  if (p.precision != MGFEM_PREC_FP64 && p.precision != MGFEM_PREC_MIXED) return why = "precision", 1;
+  if (p.cycle != MGFEM_CYCLE_V && p.cycle != MGFEM_CYCLE_W) return why = "cycle", 1;
+  const double wx = p.x_hi - p.x_lo, wy = p.y_hi - p.y_lo;
+  if (!(wx > 0.0) || !(wy > 0.0) || std::fabs(wx - wy) > 1e-12 * wx)
+    return why = "the box must be a non-empty square", 1;
+  if (N < 2 * p.coarsest_n || N % p.coarsest_n || !is_pow2(N / p.coarsest_n) || N > (1 << 15))
+    return why = "N must be coarsest_n times a power of two (>= 2), at most 32768", 1;
+  return 0;
+}
+
+}  // namespace
+
+namespace mgfem {
+hipError_t ctx_alloc(mgfem_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return e;
+  c->allocs.push_back(*p);
+  return hipMemsetAsync(*p, 0, bytes, c->s);
+}
+}  // namespace mgfem
+
+static void free_ctx(mgfem_ctx* c) {
+  if (!c) return;
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  else (void)hipDeviceSynchronize();
+  for (void* q : c->allocs) (void)hipFree(q);
+  if (c->red_host) (void)hipHostFree(c->red_host);
+  delete c;
+}
+
+extern "C" {
+
+int mgfem_default_params(mgfem_params* p) {
+  if (!p) return MGFEM_ERR_INVALID_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->stab_rule = MGFEM_STAB_PAPER;
+  p->gamma = 2.0;
+  p->lambda_fixed = 0.0;
+  p->snap_alpha = 1.75;
+  p->nu1 = 2;
+  p->nu2 = 1;
+  p->eta = 4;
+  p->coarsest_n = 4;
+  p->precision = MGFEM_PREC_FP64;
+  p->cycle = MGFEM_CYCLE_V;
+  p->x_lo = -1.0;
+  p->y_lo = -1.0;
+  p->x_hi = 1.0;
+  p->y_hi = 1.0;
+  return MGFEM_OK;
+}
+
+const char* mgfem_status_string(int code) {
+  switch (code) {
+    case MGFEM_OK: return "ok";
+    case MGFEM_ERR_INVALID_ARG: return "invalid argument";
+    case MGFEM_ERR_OOM: return "out of device memory";
+    case MGFEM_ERR_HIP: return "HIP runtime error";
+    case MGFEM_ERR_NOT_CONVERGED: return "not converged within max_cycles";
+    case MGFEM_ERR_DIVERGED: return "diverged";
+    case MGFEM_ERR_SINGULAR_COARSE: return "coarsest matrix not positive definite";
+    case MGFEM_ERR_EMPTY_DOMAIN: return "empty domain";
+    case MGFEM_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+const char* mgfem_last_error(mgfem_handle h) {
+  return h ? h->last_error.c_str() : g_setup_error.c_str();
+}
+
+int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void* stream,
+                mgfem_handle* out) {
+  if (!out) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!psi_dev) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "psi_dev is NULL");
+  mgfem_params p;
+  if (pin) p = *pin;
+  else mgfem_default_params(&p);
+  std::string why;
+  if (check_params(p, N, why)) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "invalid parameter: " + why);
+  mgfem_ctx* c = new (std::nothrow) mgfem_ctx();
+  if (!c) return fail(nullptr, MGFEM_ERR_OOM, "host allocation failed");
+  c->p = p;
+  c->s = reinterpret_cast<hipStream_t>(stream);
+  c->N = N;
+  c->h = (p.x_hi - p.x_lo) / N;
+  for (int n = N; n >= p.coarsest_n; n /= 2) {
+    Level L;
+    L.N = n;
+    L.stride = n + 1;
+    L.n = (int64_t)(n + 1) * (n + 1);
+    c->lv.push_back(L);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = MGFEM_OK;
+  auto bail = [&](int code) {
+    std::string msg = c->last_error;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    free_ctx(c);
+    return fail(nullptr, code, msg);
+  };
+#define SETUP_TRY(x)                                               \
+  do {                                                             \
+    hipError_t _e = (x);                                           \
+    if (_e != hipSuccess) {                                        \
+      c->last_error = std::string(#x) + ": " + hipGetErrorString(_e); \
+      return bail(_e == hipErrorOutOfMemory ? MGFEM_ERR_OOM : MGFEM_ERR_HIP); \
+    }                                                              \
+  } while (0)
+  SETUP_TRY(hipEventCreate(&e0));
+  SETUP_TRY(hipEventCreate(&e1));
+  SETUP_TRY(hipEventRecord(e0, c->s));
+  SETUP_TRY(ctx_alloc_t(c, &c->stats, 1));
+  {
+    Stats init{};
+    init.min_theta_bits = 0x7ff0000000000000ull;
+    SETUP_TRY(hipMemcpyAsync(c->stats, &init, sizeof(init), hipMemcpyHostToDevice, c->s));
+  }
+  const int64_t n0 = c->lv[0].n;
+  SETUP_TRY(ctx_alloc_t(c, &c->F, n0));
+  SETUP_TRY(ctx_alloc_t(c, &c->F64tmp, n0));
+  SETUP_TRY(ctx_alloc_t(c, &c->zero, n0));
+  SETUP_TRY(ctx_alloc_t(c, &c->lam, n0));
+  SETUP_TRY(ctx_alloc_t(c, &c->red_partial, 2 * kRedBlocks));
+  SETUP_TRY(ctx_alloc_t(c, &c->red_out, 2));
+  SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 2 * sizeof(double)));
+  rc = setup_geometry(c, psi_dev);
+  if (rc != MGFEM_OK) return bail(rc);
+  rc = setup_hierarchy(c);
+  if (rc != MGFEM_OK) return bail(rc);
+  SETUP_TRY(hipEventRecord(e1, c->s));
+  Stats st{};
+  SETUP_TRY(hipMemcpyAsync(&st, c->stats, sizeof(st), hipMemcpyDeviceToHost, c->s));
+  SETUP_TRY(hipStreamSynchronize(c->s));
+  float ms = 0.f;
+  SETUP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  e0 = e1 = nullptr;
+  if (st.coarse_status != 0) {
+    c->last_error = "non-positive pivot in the Cholesky factor of the coarsest operator";
+    return bail(MGFEM_ERR_SINGULAR_COARSE);
+  }
+  if (st.coarse_n > 512) {
+    c->last_error = "coarsest grid has more than 512 active nodes";
+    return bail(MGFEM_ERR_INVALID_ARG);
+  }
+  c->coarse_n = st.coarse_n;
+  mgfem_info& I = c->info;
+  I.N = N;
+  I.n_levels = (int)c->lv.size();
+  I.n_active = (int64_t)st.active;
+  for (int t = 0; t < 7; ++t) I.n_cells_by_type[t] = (int64_t)st.counts[t];
+  I.n_snapped = (int64_t)st.snapped;
+  I.n_cut_vertices = c->lv[0].cut_off[4];
+  I.coarse_n = st.coarse_n;
+  double mt, ml;
+  std::memcpy(&mt, &st.min_theta_bits, 8);
+  std::memcpy(&ml, &st.max_lambda_bits, 8);
+  I.min_theta = std::isinf(mt) ? 0.0 : mt;
+  I.max_lambda = ml;
+  I.setup_ms = ms;
+#undef SETUP_TRY
+  *out = c;
+  return MGFEM_OK;
+}
+
+int mgfem_query(mgfem_handle h, mgfem_info* info) {
+  if (!h || !info) return MGFEM_ERR_INVALID_ARG;
+  *info = h->info;
+  return MGFEM_OK;
+}
+
+int32_t mgfem_level_n(mgfem_handle h, int32_t level) {
+  if (!h || level < 0 || level >= (int)h->lv.size()) return -1;
+  return h->lv[level].N;
+}
+
+int mgfem_destroy(mgfem_handle h) {
+  if (!h) return MGFEM_ERR_INVALID_ARG;
+  free_ctx(h);
+  return MGFEM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// read c->red_out (max, sum of squares) to the host
+int read_norm(mgfem_ctx* c, double& mx, double& l2) {
+  MGFEM_HIP_TRY(hipMemcpyAsync(c->red_host, c->red_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  mx = c->red_host[0];
+  l2 = std::sqrt(c->red_host[1]);
+  return MGFEM_OK;
+}
+
+// cycles on A x = b (level-0 buffers x, b) until the relative tolerance is met
+int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cycles, bool reverse,
+            bool mixed, double* hist, int* ncyc) {
+  Level& L0 = c->lv[0];
+  double bnorm, dummy, r0, l2;
+  launch_residual_norm(c, b, c->zero, nullptr);
+  int rc = read_norm(c, bnorm, dummy);
+  if (rc) return rc;
+  launch_residual_norm(c, b, x, mixed ? c->F64tmp : nullptr);
+  rc = read_norm(c, r0, l2);
+  if (rc) return rc;
+  if (hist) hist[0] = r0;
+  double prev = r0;
+  int grow = 0, m = 0;
+  bool conv = r0 <= rel_tol * bnorm;
+  int status = MGFEM_OK;
+  if (!std::isfinite(r0)) status = MGFEM_ERR_DIVERGED;
+  while (status == MGFEM_OK && !conv && m < max_cycles) {
+    if (mixed) {
+      launch_cast_to_float(c, L0.b32, c->F64tmp, L0.n);
+      launch_zero_f(c, L0.x32, L0.n);
+      CycleOpts o;
+      o.fp32 = true;
+      o.reverse = reverse;
+      run_cycle(c, o);
+      launch_axpy_active(c, x, L0.x32);
+      launch_residual_norm(c, b, x, c->F64tmp);
+    } else {
+      L0.x = x;
+      L0.b = const_cast<double*>(b);
+      CycleOpts o;
+      o.reverse = reverse;
+      run_cycle(c, o);
+      launch_residual_norm(c, b, x, nullptr);
+    }
+    MGFEM_HIP_TRY(hipGetLastError());
+    double rm;
+    rc = read_norm(c, rm, l2);
+    if (rc) return rc;
+    ++m;
+    if (hist) hist[m] = rm;
+    if (!std::isfinite(rm)) {
+      status = MGFEM_ERR_DIVERGED;
+      break;
+    }
+    grow = rm > prev ? grow + 1 : 0;
+    if (grow >= 3) {
+      status = MGFEM_ERR_DIVERGED;
+      break;
+    }
+    prev = rm;
+    conv = rm <= rel_tol * bnorm;
+  }
+  L0.x = nullptr;
+  L0.b = nullptr;
+  if (ncyc) *ncyc = m;
+  if (status != MGFEM_OK) {
+    c->last_error = "residual not finite or growing";
+    return status;
+  }
+  if (!conv && rel_tol > 0.0) {
+    c->last_error = "tolerance not reached within max_cycles";
+    return MGFEM_ERR_NOT_CONVERGED;
+  }
+  return MGFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgfem_solve(mgfem_handle c, const double* f_dev, const double* g_dev, double rel_tol,
+                int32_t max_cycles, uint32_t flags, double* u_dev, double* res_hist_host,
+                int32_t* n_cycles) {
+  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (c->batched_member) return fail(c, MGFEM_ERR_INVALID_ARG, "batched handle: use mgfem_solve_batched");
+  if (!f_dev || !g_dev || !u_dev || max_cycles < 0)
+    return fail(c, MGFEM_ERR_INVALID_ARG, "f, g and u must be device pointers; max_cycles >= 0");
+  launch_rhs(c, f_dev, g_dev, c->F);
+  if (flags & MGFEM_SOLVE_WARM_START) launch_mask_inactive(c, u_dev);
+  else launch_zero(c, u_dev, c->lv[0].n);
+  MGFEM_HIP_TRY(hipGetLastError());
+  int nc = 0;
+  int rc = iterate(c, u_dev, c->F, rel_tol, max_cycles, false, c->p.precision == MGFEM_PREC_MIXED,
+                   res_hist_host, &nc);
+  if (n_cycles) *n_cycles = nc;
+  return rc;
+}
+
+int mgfem_adjoint(mgfem_handle c, const double* dJdu_dev, double rel_tol, int32_t max_cycles,
+                  double* lam_dev, double* dJdf_dev, double* dJdg_dev, double* res_hist_host,
+                  int32_t* n_cycles) {
+  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (!dJdu_dev || max_cycles < 0) return fail(c, MGFEM_ERR_INVALID_ARG, "dJdu must be a device pointer");
+  double* lam = lam_dev ? lam_dev : c->lam;
+  launch_zero(c, lam, c->lv[0].n);
+  // the adjoint right-hand side must vanish off the active nodes
+  launch_sub_active(c, c->F, dJdu_dev, c->zero);
+  MGFEM_HIP_TRY(hipGetLastError());
+  int nc = 0;
+  int rc = iterate(c, lam, c->F, rel_tol, max_cycles, true, false, res_hist_host, &nc);
+  if (n_cycles) *n_cycles = nc;
+  if (rc != MGFEM_OK && rc != MGFEM_ERR_NOT_CONVERGED) return rc;
+  if (dJdf_dev) launch_stencil_apply(c, c->M, lam, dJdf_dev, false);
+  if (dJdg_dev) launch_stencil_apply(c, c->G, lam, dJdg_dev, true);
+  MGFEM_HIP_TRY(hipGetLastError());
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return rc;
+}
+
+int mgfem_misfit(mgfem_handle c, const double* u_dev, const double* ut_dev, double* J_host,
+                 double* dJdu_dev) {
+  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (!u_dev || !ut_dev || !J_host) return fail(c, MGFEM_ERR_INVALID_ARG, "u, ut and J must be given");
+  double* e = c->F64tmp;
+  double* Me = dJdu_dev ? dJdu_dev : c->lam;
+  launch_sub_active(c, e, u_dev, ut_dev);
+  launch_stencil_apply(c, c->M, e, Me, false);
+  launch_dot_reduce(c, e, Me);
+  MGFEM_HIP_TRY(hipGetLastError());
+  double mx, l2;
+  int rc = read_norm(c, mx, l2);
+  if (rc) return rc;
+  *J_host = 0.5 * c->red_host[1];
+  return MGFEM_OK;
+}
+
+int mgfem_smooth(mgfem_handle c, int32_t level, double* x_dev, const double* b_dev, int32_t steps,
+                 int32_t reverse) {
+  if (!c || level < 0 || level + 1 >= (int)c->lv.size() || !x_dev || !b_dev || steps < 0)
+    return c ? fail(c, MGFEM_ERR_INVALID_ARG, "bad level (the coarsest has no smoother) or pointer")
+             : MGFEM_ERR_INVALID_ARG;
+  Level& L = c->lv[level];
+  double* sx = L.x;
+  double* sb = L.b;
+  L.x = x_dev;
+  L.b = const_cast<double*>(b_dev);
+  for (int s = 0; s < steps; ++s) smooth_level(c, level, reverse != 0, false);
+  L.x = sx;
+  L.b = sb;
+  MGFEM_HIP_TRY(hipGetLastError());
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return MGFEM_OK;
+}
+
+int mgfem_export(mgfem_handle c, int32_t what, int32_t level, double* dst) {
+  if (!c || !dst || level < 0 || level >= (int)c->lv.size()) return MGFEM_ERR_INVALID_ARG;
+  Level& L = c->lv[level];
+  const int64_t n = L.n, nc = (int64_t)c->N * c->N;
+  const bool l0 = level == 0;
+  switch (what) {
+    case MGFEM_EXPORT_PSI:
+      if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
+      launch_copy(c, dst, c->psi, n);
+      break;
+    case MGFEM_EXPORT_CELL_TYPE:
+      if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
+      launch_u8_to_f64(c, c->cell_type, dst, nc);
+      break;
+    case MGFEM_EXPORT_CELL_LAMBDA:
+      if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
+      launch_copy(c, dst, c->cell_lambda, nc);
+      break;
+    case MGFEM_EXPORT_A: launch_copy(c, dst, L.A, 9 * n); break;
+    case MGFEM_EXPORT_M:
+      if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
+      launch_copy(c, dst, c->M, 9 * n);
+      break;
+    case MGFEM_EXPORT_G:
+      if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
+      launch_copy(c, dst, c->G, 9 * n);
+      break;
+    case MGFEM_EXPORT_NODE_FLAGS: launch_u8_to_f64(c, L.flags, dst, n); break;
+    case MGFEM_EXPORT_RHS:
+      if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
+      launch_copy(c, dst, c->F, n);
+      break;
+    default: return fail(c, MGFEM_ERR_INVALID_ARG, "unknown export");
+  }
+  MGFEM_HIP_TRY(hipGetLastError());
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return MGFEM_OK;
+}
+
+}  // extern "C"
