@@ -182,6 +182,9 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
     return bail(MGFEM_ERR_INVALID_ARG);
   }
   c->coarse_n = st.coarse_n;
+  rc = build_plans(c);
+  if (rc != MGFEM_OK) return bail(rc);
+  SETUP_TRY(hipStreamSynchronize(c->s));
   mgfem_info& I = c->info;
   I.N = N;
   I.n_levels = (int)c->lv.size();
@@ -231,7 +234,8 @@ int read_norm(mgfem_ctx* c, double& mx, double& l2) {
   return MGFEM_OK;
 }
 
-// cycles on A x = b (level-0 buffers x, b) until the relative tolerance is met
+// cycles on A x = b (x, b on level 0) until the relative tolerance is met;
+// x is the caller's buffer and receives the result
 int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cycles, bool reverse,
             bool mixed, double* hist, int* ncyc) {
   Level& L0 = c->lv[0];
@@ -243,6 +247,10 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   rc = read_norm(c, r0, l2);
   if (rc) return rc;
   if (hist) hist[0] = r0;
+  L0.X[0] = x;
+  L0.b = const_cast<double*>(b);
+  L0.cur = 0;
+  if (!mixed) gather_snap(c, 0, false);
   double prev = r0;
   int grow = 0, m = 0;
   bool conv = r0 <= rel_tol * bnorm;
@@ -251,20 +259,19 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   while (status == MGFEM_OK && !conv && m < max_cycles) {
     if (mixed) {
       launch_cast_to_float(c, L0.b32, c->F64tmp, L0.n);
-      launch_zero_f(c, L0.x32, L0.n);
+      L0.cur = 0;
+      launch_zero_f(c, L0.X32[0], L0.n);
       CycleOpts o;
       o.fp32 = true;
       o.reverse = reverse;
       run_cycle(c, o);
-      launch_axpy_active(c, x, L0.x32);
+      launch_axpy_active(c, x, L0.X32[L0.cur]);
       launch_residual_norm(c, b, x, c->F64tmp);
     } else {
-      L0.x = x;
-      L0.b = const_cast<double*>(b);
       CycleOpts o;
       o.reverse = reverse;
       run_cycle(c, o);
-      launch_residual_norm(c, b, x, nullptr);
+      launch_residual_norm(c, b, L0.X[L0.cur], nullptr);
     }
     MGFEM_HIP_TRY(hipGetLastError());
     double rm;
@@ -284,8 +291,12 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     prev = rm;
     conv = rm <= rel_tol * bnorm;
   }
-  L0.x = nullptr;
+  if (!mixed && L0.cur == 1) launch_copy(c, x, L0.X[1], L0.n);
+  MGFEM_HIP_TRY(hipGetLastError());
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  L0.X[0] = nullptr;
   L0.b = nullptr;
+  L0.cur = 0;
   if (ncyc) *ncyc = m;
   if (status != MGFEM_OK) {
     c->last_error = "residual not finite or growing";
@@ -364,13 +375,17 @@ int mgfem_smooth(mgfem_handle c, int32_t level, double* x_dev, const double* b_d
     return c ? fail(c, MGFEM_ERR_INVALID_ARG, "bad level (the coarsest has no smoother) or pointer")
              : MGFEM_ERR_INVALID_ARG;
   Level& L = c->lv[level];
-  double* sx = L.x;
+  double* sx = L.X[0];
   double* sb = L.b;
-  L.x = x_dev;
+  L.X[0] = x_dev;
   L.b = const_cast<double*>(b_dev);
+  L.cur = 0;
+  gather_snap(c, level, false);
   for (int s = 0; s < steps; ++s) smooth_level(c, level, reverse != 0, false);
-  L.x = sx;
+  if (L.cur == 1) launch_copy(c, x_dev, L.X[1], L.n);
+  L.X[0] = sx;
   L.b = sb;
+  L.cur = 0;
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   return MGFEM_OK;

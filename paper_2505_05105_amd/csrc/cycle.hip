@@ -1,13 +1,7 @@
-// The multigrid cycle on the device: Gauss-Seidel smoothing in four colours
-// plus extra sweeps on the cut-cell vertices, residual, restriction,
-// prolongation with correction, the coarsest exact solve, and the residual
-// norms of the convergence history (sections 3 and 5).
-//
-// Colour c(i,j) = (i mod 2) + 2 (j mod 2).  The 9-point stencil never couples
-// two nodes of one colour, so a colour phase updates all of its nodes at once
-// and equals the Gauss-Seidel update of those nodes in any order.  Rows marked
-// as not stored are the interior Q1 stencil (8/3 centre, -1/3 neighbours) and
-// are applied without reading the stencil planes.
+// Level-0 vector kernels around the cycle: the load vector F = M f + G g,
+// residual norms of the convergence history (l-infinity, section 3.1, and l2),
+// stencil products for the gradients, masks, copies and casts.  Rows marked
+// as not stored are the interior Q1 stencil (8/3 centre, -1/3 neighbours).
 #include <cmath>
 
 #include "mgfem_internal.h"
@@ -15,7 +9,6 @@
 namespace mgfem {
 namespace {
 
-constexpr int kTbX = 64, kTbY = 4;
 
 // max that propagates NaN (so a diverged solve is reported, not hidden)
 __device__ inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
@@ -58,121 +51,6 @@ __device__ inline T row_times_x(const LevelView<T>& v, int i, int j, int64_t k, 
   const T nb = (x[k - v.s - 1] + x[k - v.s] + x[k - v.s + 1]) + (x[k - 1] + x[k + 1]) +
                (x[k + v.s - 1] + x[k + v.s] + x[k + v.s + 1]);
   return diag * x[k] - nb / T(3);
-}
-
-// one colour phase over the nodes (i0 + 2 ti, j0 + 2 tj) of the bounding box
-template <class T>
-__global__ void k_gs_colour(LevelView<T> v, int i0, int j0, int ni, int nj) {
-  const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-  const int tj = blockIdx.y * blockDim.y + threadIdx.y;
-  if (ti >= ni || tj >= nj) return;
-  const int i = i0 + 2 * ti, j = j0 + 2 * tj;
-  const int64_t k = i + (int64_t)j * v.s;
-  const uint8_t f = v.fl[k];
-  if (!(f & kFlagActive)) return;
-  T diag;
-  const T ax = row_times_x(v, i, j, k, f, diag);
-  v.x[k] += (v.b[k] - ax) / diag;
-}
-
-// one colour phase over a list of nodes (extra smoothing on cut-cell vertices)
-template <class T>
-__global__ void k_gs_list(LevelView<T> v, const int* __restrict__ list, int cnt) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= cnt) return;
-  const int64_t k = list[t];
-  const int i = (int)(k % v.s), j = (int)(k / v.s);
-  const uint8_t f = v.fl[k];
-  T diag;
-  const T ax = row_times_x(v, i, j, k, f, diag);
-  v.x[k] += (v.b[k] - ax) / diag;
-}
-
-template <class T>
-__global__ void k_residual(LevelView<T> v, int i0, int j0, int ni, int nj) {
-  const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-  const int tj = blockIdx.y * blockDim.y + threadIdx.y;
-  if (ti >= ni || tj >= nj) return;
-  const int i = i0 + ti, j = j0 + tj;
-  const int64_t k = i + (int64_t)j * v.s;
-  const uint8_t f = v.fl[k];
-  if (!(f & kFlagActive)) return;
-  T diag;
-  v.r[k] = v.b[k] - row_times_x(v, i, j, k, f, diag);
-}
-
-// coarse b = R r (weights 1, 1/2, 1/4 of the shape-function relation), coarse x = 0
-template <class T>
-__global__ void k_restrict(const T* __restrict__ rf, int Nf, LevelView<T> c, int I0, int J0, int ni,
-                           int nj) {
-  const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-  const int tj = blockIdx.y * blockDim.y + threadIdx.y;
-  if (ti >= ni || tj >= nj) return;
-  const int I = I0 + ti, J = J0 + tj;
-  const int64_t kc = I + (int64_t)J * c.s;
-  if (!(c.fl[kc] & kFlagActive)) return;
-  const int sf = Nf + 1;
-  const int fi = 2 * I, fj = 2 * J;
-  const int64_t fk = fi + (int64_t)fj * sf;
-  const bool w = fi > 0, e = fi < Nf, so = fj > 0, no = fj < Nf;
-  T row0 = rf[fk] + T(0.5) * ((w ? rf[fk - 1] : T(0)) + (e ? rf[fk + 1] : T(0)));
-  T rows = T(0), rown = T(0);
-  if (so) {
-    const int64_t q = fk - sf;
-    rows = rf[q] + T(0.5) * ((w ? rf[q - 1] : T(0)) + (e ? rf[q + 1] : T(0)));
-  }
-  if (no) {
-    const int64_t q = fk + sf;
-    rown = rf[q] + T(0.5) * ((w ? rf[q - 1] : T(0)) + (e ? rf[q + 1] : T(0)));
-  }
-  c.b[kc] = row0 + T(0.5) * (rows + rown);
-  c.x[kc] = T(0);
-}
-
-// fine x += P coarse x at active fine nodes (bilinear interpolation)
-template <class T>
-__global__ void k_prolong(const T* __restrict__ xc, int Nc, LevelView<T> f, int i0, int j0, int ni,
-                          int nj) {
-  const int ti = blockIdx.x * blockDim.x + threadIdx.x;
-  const int tj = blockIdx.y * blockDim.y + threadIdx.y;
-  if (ti >= ni || tj >= nj) return;
-  const int i = i0 + ti, j = j0 + tj;
-  const int64_t k = i + (int64_t)j * f.s;
-  if (!(f.fl[k] & kFlagActive)) return;
-  const int sc = Nc + 1;
-  const int I = i >> 1, J = j >> 1;
-  const int64_t kc = I + (int64_t)J * sc;
-  T val;
-  if (!(i & 1) && !(j & 1)) {
-    val = xc[kc];
-  } else if ((i & 1) && !(j & 1)) {
-    val = T(0.5) * (xc[kc] + xc[kc + 1]);
-  } else if (!(i & 1) && (j & 1)) {
-    val = T(0.5) * (xc[kc] + xc[kc + sc]);
-  } else {
-    val = T(0.25) * ((xc[kc] + xc[kc + 1]) + (xc[kc + sc] + xc[kc + sc + 1]));
-  }
-  f.x[k] += val;
-}
-
-// exact solve on the coarsest level with the stored Cholesky factor (float64)
-template <class T>
-__global__ void k_coarse_solve(const double* __restrict__ Lm, const int* __restrict__ idx, const int* cnp,
-                               const T* __restrict__ b, T* __restrict__ x) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int cn = *cnp;
-  double y[512];
-  for (int i = 0; i < cn; ++i) {
-    double v = (double)b[idx[i]];
-    for (int t = 0; t < i; ++t) v -= Lm[i * cn + t] * y[t];
-    y[i] = v / Lm[i * cn + i];
-  }
-  for (int i = cn - 1; i >= 0; --i) {
-    double v = y[i];
-    for (int t = i + 1; t < cn; ++t) v -= Lm[t * cn + i] * y[t];
-    y[i] = v / Lm[i * cn + i];
-  }
-  for (int i = 0; i < cn; ++i) x[idx[i]] = (T)y[i];
 }
 
 // residual norms of level 0: per-block max |r| and sum r^2 (fixed block count,
@@ -323,113 +201,7 @@ __global__ void k_axpy_active(const uint8_t* __restrict__ fl, double* __restrict
 
 inline unsigned nblk(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); }
 
-template <class T>
-LevelView<T> view(mgfem_ctx* c, int l);
-template <>
-LevelView<double> view<double>(mgfem_ctx* c, int l) {
-  Level& L = c->lv[l];
-  return LevelView<double>{L.A, L.flags, L.x, L.b, L.r, L.N, L.stride, L.n};
-}
-template <>
-LevelView<float> view<float>(mgfem_ctx* c, int l) {
-  Level& L = c->lv[l];
-  return LevelView<float>{L.A32, L.flags, L.x32, L.b32, L.r32, L.N, L.stride, L.n};
-}
-
-template <class T>
-void colour_phase(mgfem_ctx* c, int l, int col) {
-  Level& L = c->lv[l];
-  if (L.empty()) return;
-  const int cx = col & 1, cy = col >> 1;
-  const int i0 = L.bbox[0] + ((cx - L.bbox[0]) & 1);
-  const int j0 = L.bbox[2] + ((cy - L.bbox[2]) & 1);
-  if (i0 > L.bbox[1] || j0 > L.bbox[3]) return;
-  const int ni = (L.bbox[1] - i0) / 2 + 1, nj = (L.bbox[3] - j0) / 2 + 1;
-  dim3 grid(nblk(ni, kTbX), nblk(nj, kTbY));
-  hipLaunchKernelGGL(k_gs_colour<T>, grid, dim3(kTbX, kTbY), 0, c->s, view<T>(c, l), i0, j0, ni, nj);
-}
-
-template <class T>
-void list_phase(mgfem_ctx* c, int l, int col) {
-  Level& L = c->lv[l];
-  const int cnt = L.cut_off[col + 1] - L.cut_off[col];
-  if (cnt <= 0) return;
-  hipLaunchKernelGGL(k_gs_list<T>, dim3(nblk(cnt, 256)), dim3(256), 0, c->s, view<T>(c, l),
-                     L.cut_list + L.cut_off[col], cnt);
-}
-
-template <class T>
-void smooth(mgfem_ctx* c, int l, bool reverse) {
-  const int eta = c->p.eta;
-  if (!reverse) {
-    for (int col = 0; col < 4; ++col) colour_phase<T>(c, l, col);
-    for (int e = 0; e < eta; ++e)
-      for (int col = 0; col < 4; ++col) list_phase<T>(c, l, col);
-  } else {
-    for (int e = 0; e < eta; ++e)
-      for (int col = 3; col >= 0; --col) list_phase<T>(c, l, col);
-    for (int col = 3; col >= 0; --col) colour_phase<T>(c, l, col);
-  }
-}
-
-template <class T>
-void bbox_grid(const Level& L, dim3& grid, int& ni, int& nj) {
-  ni = L.bbox[1] - L.bbox[0] + 1;
-  nj = L.bbox[3] - L.bbox[2] + 1;
-  grid = dim3(nblk(ni, kTbX), nblk(nj, kTbY));
-}
-
-template <class T>
-void cycle_level(mgfem_ctx* c, int l, bool reverse) {
-  const int nl = (int)c->lv.size();
-  Level& L = c->lv[l];
-  if (l == nl - 1) {
-    LevelView<T> v = view<T>(c, l);
-    hipLaunchKernelGGL(k_coarse_solve<T>, dim3(1), dim3(64), 0, c->s, c->coarse_L, c->coarse_idx,
-                       &c->stats->coarse_n, (const T*)v.b, v.x);
-    return;
-  }
-  const int pre = reverse ? c->p.nu2 : c->p.nu1;
-  const int post = reverse ? c->p.nu1 : c->p.nu2;
-  for (int s = 0; s < pre; ++s) smooth<T>(c, l, reverse);
-  if (!L.empty()) {
-    dim3 grid;
-    int ni, nj;
-    bbox_grid<T>(L, grid, ni, nj);
-    hipLaunchKernelGGL(k_residual<T>, grid, dim3(kTbX, kTbY), 0, c->s, view<T>(c, l), L.bbox[0],
-                       L.bbox[2], ni, nj);
-  }
-  Level& C = c->lv[l + 1];
-  if (!C.empty()) {
-    dim3 grid;
-    int ni, nj;
-    bbox_grid<T>(C, grid, ni, nj);
-    hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kTbX, kTbY), 0, c->s, (const T*)view<T>(c, l).r, L.N,
-                       view<T>(c, l + 1), C.bbox[0], C.bbox[2], ni, nj);
-  }
-  const int gstar = c->p.cycle == MGFEM_CYCLE_W ? 2 : 1;
-  for (int g = 0; g < gstar; ++g) cycle_level<T>(c, l + 1, reverse);
-  if (!L.empty()) {
-    dim3 grid;
-    int ni, nj;
-    bbox_grid<T>(L, grid, ni, nj);
-    hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kTbX, kTbY), 0, c->s, (const T*)view<T>(c, l + 1).x,
-                       C.N, view<T>(c, l), L.bbox[0], L.bbox[2], ni, nj);
-  }
-  for (int s = 0; s < post; ++s) smooth<T>(c, l, reverse);
-}
-
 }  // namespace
-
-void run_cycle(mgfem_ctx* c, const CycleOpts& o) {
-  if (o.fp32) cycle_level<float>(c, 0, o.reverse);
-  else cycle_level<double>(c, 0, o.reverse);
-}
-
-void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32) {
-  if (fp32) smooth<float>(c, l, reverse);
-  else smooth<double>(c, l, reverse);
-}
 
 void launch_rhs(mgfem_ctx* c, const double* f, const double* g, double* F) {
   const int64_t n = c->lv[0].n;
@@ -467,8 +239,7 @@ void launch_axpy_active(mgfem_ctx* c, double* u, const float* e) {
 // ||F - A u||_inf and ||.||_2^2 of level 0 into c->red_out[0..1]; r_out optional
 void launch_residual_norm(mgfem_ctx* c, const double* F, const double* u, double* r_out) {
   Level& L = c->lv[0];
-  LevelView<double> v = view<double>(c, 0);
-  v.x = const_cast<double*>(u);
+  LevelView<double> v{L.A, L.flags, const_cast<double*>(u), nullptr, nullptr, L.N, L.stride, L.n};
   const int ni = L.bbox[1] - L.bbox[0] + 1, nj = L.bbox[3] - L.bbox[2] + 1;
   const int64_t tot = (int64_t)ni * nj;
   const int nb = (int)std::min<int64_t>(kRedBlocks, (tot + 255) / 256);

@@ -141,7 +141,8 @@ __global__ void k_row_scatter(const uint8_t* __restrict__ fl, int N, int j0, int
 
 // gather and factor the coarsest active block (one thread: at most a few hundred unknowns)
 __global__ void k_coarse_factor(const double* __restrict__ A, const uint8_t* __restrict__ fl, int N,
-                                double* __restrict__ Lm, int* __restrict__ idx, Stats* st) {
+                                double* __restrict__ Lm, int* __restrict__ idx, double* __restrict__ inv,
+                                Stats* st) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int s = N + 1;
   const int64_t n = (int64_t)s * s;
@@ -177,6 +178,21 @@ __global__ void k_coarse_factor(const double* __restrict__ A, const uint8_t* __r
   }
   st->coarse_status = status;
   st->coarse_n = cn;
+  if (status) return;
+  // explicit inverse A^{-1} = L^{-T} L^{-1}, one column at a time
+  for (int col = 0; col < cn; ++col) {
+    double* x = inv + (int64_t)col * cn;  // column stored as a row (A^{-1} is symmetric)
+    for (int i = 0; i < cn; ++i) {
+      double v = (i == col) ? 1.0 : 0.0;
+      for (int t = 0; t < i; ++t) v -= Lm[i * cn + t] * x[t];
+      x[i] = v / Lm[i * cn + i];
+    }
+    for (int i = cn - 1; i >= 0; --i) {
+      double v = x[i];
+      for (int t = i + 1; t < cn; ++t) v -= Lm[t * cn + i] * x[t];
+      x[i] = v / Lm[i * cn + i];
+    }
+  }
 }
 
 __global__ void k_to_float(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
@@ -263,17 +279,17 @@ int setup_hierarchy(mgfem_ctx* c) {
   for (int l = 0; l < nl; ++l) {
     Level& L = c->lv[l];
     if (l > 0) {
-      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.x, L.n));
+      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.X[0], L.n));
       MGFEM_HIP_TRY(ctx_alloc_t(c, &L.b, L.n));
     }
-    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.r, L.n));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.X[1], L.n));
     if (mixed) {
       MGFEM_HIP_TRY(ctx_alloc_t(c, &L.A32, 9 * L.n));
       hipLaunchKernelGGL(k_to_float, dim3(nblk(9 * L.n, tb)), dim3(tb), 0, c->s, L.A, L.A32,
                          9 * L.n);
-      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.x32, L.n));
+      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.X32[0], L.n));
+      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.X32[1], L.n));
       MGFEM_HIP_TRY(ctx_alloc_t(c, &L.b32, L.n));
-      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.r32, L.n));
     }
   }
   // coarsest factorisation
@@ -281,8 +297,9 @@ int setup_hierarchy(mgfem_ctx* c) {
   const int cmax = (int)Lc.n;
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->coarse_L, (int64_t)cmax * cmax));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->coarse_idx, cmax));
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cplan.inv, (int64_t)cmax * cmax));
   hipLaunchKernelGGL(k_coarse_factor, dim3(1), dim3(64), 0, c->s, Lc.A, Lc.flags, Lc.N, c->coarse_L,
-                     c->coarse_idx, c->stats);
+                     c->coarse_idx, c->cplan.inv, c->stats);
   MGFEM_HIP_TRY(hipGetLastError());
   return MGFEM_OK;
 }

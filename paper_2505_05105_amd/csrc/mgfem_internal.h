@@ -33,6 +33,22 @@ constexpr int kFlagCut = 4;
 constexpr int kExternal = 0, kTriangle = 1, kQuad = 2, kPentagon = 3, kInternal = 4,
               kSaddleSplit = 5, kSaddleHex = 6;
 
+// Groups of cut vertices for the extra-smoothing kernel: each group owns the
+// cut vertices of one spatial tile and carries the closure it needs (every cut
+// vertex within 4 eta nodes of the tile), so that all 4 eta colour phases of
+// one smoothing step run inside one workgroup's LDS.
+struct CutPlan {
+  bool ok = false;
+  int ngroups = 0;
+  int* g_info = nullptr;    // 9 ints per group: cl_off, cl_cnt, ext_off, ext_cnt, colour offsets[5]
+  int* cl_node = nullptr;   // closure node index
+  int* cl_q = nullptr;      // closure node position in the level's cut list
+  uint8_t* cl_own = nullptr;
+  int16_t* cl_nbr = nullptr;  // 8 per closure node: <cl_cnt closure slot, >= cl_cnt external slot, -1 none
+  int* ext_src = nullptr;   // >= 0 node read from x; < 0 -(1+q) read from the cut-value snapshot
+  int max_cl = 0, max_ext = 0;
+};
+
 struct Level {
   int N = 0;
   int stride = 0;  // N + 1
@@ -41,12 +57,32 @@ struct Level {
   float* A32 = nullptr;
   uint8_t* flags = nullptr;
   uint8_t* cellcut = nullptr;  // N*N, 1 on cut cells of this level
-  double *x = nullptr, *b = nullptr, *r = nullptr;
-  float *x32 = nullptr, *b32 = nullptr, *r32 = nullptr;
-  int* cut_list = nullptr;  // concatenated colour lists
+  double* X[2] = {nullptr, nullptr};  // ping-pong iterates (level 0: X[0] is the caller's)
+  float* X32[2] = {nullptr, nullptr};
+  double* b = nullptr;
+  float* b32 = nullptr;
+  int cur = 0;                // which X holds the current iterate (host-side state)
+  int* cut_list = nullptr;    // concatenated colour lists of the cut vertices
   int cut_off[5] = {0, 0, 0, 0, 0};
+  int* cutpos = nullptr;      // per node: position in cut_list, or -1
+  double* snap = nullptr;     // cut-vertex values after the last full sweep
+  float* snap32 = nullptr;
+  CutPlan cp;
   int bbox[4] = {1, 0, 1, 0};  // i_lo, i_hi, j_lo, j_hi of active nodes (inclusive)
   bool empty() const { return bbox[0] > bbox[1]; }
+};
+
+// The coarsest levels run inside one workgroup, every array in LDS.
+struct CoarsePlan {
+  int lc = -1;            // first level of the single-workgroup part (-1: none)
+  int* desc = nullptr;    // per level descriptor (see smoother.hip)
+  double* coef = nullptr; // compact stored stencils of those levels
+  float* coef32 = nullptr;
+  int16_t* slot = nullptr;
+  int16_t* cutl = nullptr;
+  double* inv = nullptr;  // inverse of the coarsest active block (float64)
+  int ndesc = 0;
+  int lds64 = 0, lds32 = 0;
 };
 
 struct Stats {
@@ -78,9 +114,11 @@ struct mgfem_ctx {
   double* zero = nullptr;    // all-zero vector of level 0
   double* lam = nullptr;     // adjoint state when the caller passes none
   // coarsest exact solve
-  double* coarse_L = nullptr;  // cn x cn lower Cholesky factor
+  double* coarse_L = nullptr;  // cn x cn lower Cholesky factor, then its inverse
   int* coarse_idx = nullptr;   // cn node indices
   int coarse_n = 0;
+  mgfem::CoarsePlan cplan;
+  int tile_cfg = 0;            // sweep tile shape selection for large levels
   // reductions
   double* red_partial = nullptr;  // 2 * kRedBlocks
   double* red_out = nullptr;      // 2 doubles on device
@@ -125,9 +163,12 @@ struct CycleOpts {
   bool reverse = false;  // transposed cycle (adjoint)
   bool fp32 = false;     // float inner cycle
 };
-// one cycle on level 0 with x = lv[0].x*, b = lv[0].b* (pointers set by the caller)
+// one cycle on level 0 from its current iterate X[cur] and right-hand side b
 void run_cycle(mgfem_ctx* c, const CycleOpts& o);
 void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32);
+void gather_snap(mgfem_ctx* c, int l, bool fp32);
+int build_plans(mgfem_ctx* c);  // cut groups and the coarse single-workgroup layout
+void set_kernel_attributes();
 
 }  // namespace mgfem
 
