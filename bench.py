@@ -24,6 +24,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fine-grid DOF/s to 1e-10 rel. residual at N=4096 (FP64 vs mixed); HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+SWEEP_KERNEL = "k_sweep<double, 64, 64, 512>"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
+
+
+def source_hash():
+    """Hash of the sources of the profiled kernel (counters go stale when they change)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("smoother.hip", "mgfem_internal.h"):
+        with open(os.path.join(ROOT, "paper_2505_05105_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed counter runs,
+    or None when they were taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def parse():
@@ -38,6 +64,8 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--extras", action="store_true", help="also time the adjoint and batched forms")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the solves, run a plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -115,14 +143,23 @@ def main():
     for _ in range(args.warmup):
         hist = run(s64, u)
     torch.cuda.synchronize()
+    s64.profile(True)  # HIP events around every launch of the sweep kernel in the timed steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         hist = run(s64, u)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    prof = s64.profile_read(0)
+    s64.profile(False)
     ms = (t1 - t0) * 1e3 / args.steps
     cycles = len(hist) - 1
     log(f"[bench] fp64: {ms:.3f} ms/solve, {cycles} cycles, {dof / (ms * 1e-3) / 1e9:.3f} GDOF/s")
+    avg_ms = prof["total_ms"] / max(prof["launches"], 1)
+    alg = prof["alg_bytes"] / max(prof["launches"], 1)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+    log(f"[bench] {SWEEP_KERNEL}: {prof['launches']} launches, avg {avg_ms * 1e3:.2f} us, "
+        f"{alg / 1e6:.1f} MB algorithmic -> {achieved:.0f} GB/s")
 
     out = {
         "metric": METRIC, "value": dof / (ms * 1e-3), "unit": "DOF/s", "n_gpus": 1,
@@ -134,6 +171,11 @@ def main():
                    "grid_nodes": (N + 1) ** 2, "cycles": cycles, "precision": "fp64"},
         "setup_ms": info["setup_ms"],
         "final_rel_residual": float(hist[-1] / hist[0]),
+        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": alg,
+                     "launches": prof["launches"]},
+        "levels": [dict(N=s64.level_n(l), **s64.level_counts(l)) for l in range(info["n_levels"])],
     }
 
     if not args.no_mixed:
@@ -155,6 +197,17 @@ def main():
                         "speedup_vs_fp64": ms / msm}
         log(f"[bench] mixed: {msm:.3f} ms/solve, {len(hm) - 1} cycles, err vs fp64 {err:.2e}")
         smx.close()
+
+    if args.copy_probe:
+        # a plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for it calibrates the counters
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        torch.neg(a, out=b)  # one elementwise kernel: reads 512 MiB, writes 512 MiB
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = a.numel() * 8
+        del a, b
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")

@@ -194,6 +194,27 @@ int32_t mgfem_level_n(mgfem_handle h, int32_t level);
 int mgfem_smooth(mgfem_handle h, int32_t level, double* x_dev, const double* b_dev,
                  int32_t steps, int32_t reverse);
 
+/* Per-level row counts: active rows, rows whose stencil is read from the
+ * stored planes (the others are the interior Q1 stencil), extra-smoothing
+ * vertices.  Any output pointer may be NULL. */
+int mgfem_level_counts(mgfem_handle h, int32_t level, int64_t* n_active, int64_t* n_stored,
+                       int64_t* n_cut);
+
+/*
+ * Kernel timing inside solves, for roofline measurements.  While enabled,
+ * every launch of the profiled kernel class is bracketed by HIP events on the
+ * handle's stream; after each solve the durations, the launch count and the
+ * algorithmic bytes of those launches are accumulated.  Class 0 is the
+ * float64 full-sweep kernel of the finest level;
+ * its algorithmic bytes per launch are 25 per active row (iterate read and
+ * written, right-hand side, flag byte) plus 72 per stored row, plus 8 per
+ * active coarse row when the sweep applies the prolongation.
+ * mgfem_profile resets the counters.
+ */
+int mgfem_profile(mgfem_handle h, int32_t enable);
+int mgfem_profile_read(mgfem_handle h, int32_t kernel_class, int64_t* launches, double* total_ms,
+                       double* alg_bytes);
+
 /* Release the handle and all of its device memory. */
 int mgfem_destroy(mgfem_handle h);
 

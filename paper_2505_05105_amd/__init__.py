@@ -133,6 +133,22 @@ class Solver:
                                            1 if reverse else 0), self.handle)
         return x
 
+    def level_counts(self, level):
+        a, s, c = C.c_int64(), C.c_int64(), C.c_int64()
+        _lib.check(_lib.lib().mgfem_level_counts(self.handle, level, C.byref(a), C.byref(s), C.byref(c)),
+                   self.handle)
+        return {"n_active": a.value, "n_stored": s.value, "n_cut": c.value}
+
+    def profile(self, enable=True):
+        """Enable HIP-event timing of the profiled kernel class (resets the counters)."""
+        _lib.check(_lib.lib().mgfem_profile(self.handle, 1 if enable else 0), self.handle)
+
+    def profile_read(self, kernel_class=0):
+        n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+        _lib.check(_lib.lib().mgfem_profile_read(self.handle, kernel_class, C.byref(n), C.byref(ms),
+                                                 C.byref(b)), self.handle)
+        return {"launches": n.value, "total_ms": ms.value, "alg_bytes": b.value}
+
     def close(self):
         if getattr(self, "handle", None):
             _lib.lib().mgfem_destroy(self.handle)

@@ -25,6 +25,7 @@ EXPORTED = (
     "mgfem_default_params", "mgfem_setup", "mgfem_solve", "mgfem_adjoint", "mgfem_misfit",
     "mgfem_query", "mgfem_export", "mgfem_level_n", "mgfem_smooth", "mgfem_destroy",
     "mgfem_status_string", "mgfem_last_error", "mgfem_setup_batched", "mgfem_solve_batched",
+    "mgfem_level_counts", "mgfem_profile", "mgfem_profile_read",
 )
 
 
@@ -76,6 +77,10 @@ def lib():
                                           C.POINTER(P)]),
         "mgfem_solve_batched": (C.c_int, [P, C.POINTER(P), C.POINTER(P), D, I32, C.POINTER(P), DP,
                                           C.POINTER(I32)]),
+        "mgfem_level_counts": (C.c_int, [P, I32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                         C.POINTER(C.c_int64)]),
+        "mgfem_profile": (C.c_int, [P, I32]),
+        "mgfem_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP, DP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

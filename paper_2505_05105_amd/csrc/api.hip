@@ -53,10 +53,41 @@ hipError_t ctx_alloc(mgfem_ctx* c, void** p, size_t bytes) {
 }
 }  // namespace mgfem
 
+namespace mgfem {
+int prof_begin(mgfem_ctx* c, int kernel_class, double bytes) {
+  Profiler& P = c->prof;
+  const int slot = (int)P.pending.size();
+  while ((int)P.ev.size() < 2 * (slot + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    P.ev.push_back(e);
+  }
+  if (hipEventRecord(P.ev[2 * slot], c->s) != hipSuccess) return -1;
+  P.pending.push_back({kernel_class, bytes});
+  return slot;
+}
+void prof_end(mgfem_ctx* c, int slot) { (void)hipEventRecord(c->prof.ev[2 * slot + 1], c->s); }
+void prof_collect(mgfem_ctx* c) {
+  Profiler& P = c->prof;
+  if (P.pending.empty()) return;
+  (void)hipStreamSynchronize(c->s);
+  for (size_t i = 0; i < P.pending.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]) != hipSuccess) continue;
+    const int k = P.pending[i].first;
+    P.launches[k] += 1;
+    P.ms[k] += ms;
+    P.bytes[k] += P.pending[i].second;
+  }
+  P.pending.clear();
+}
+}  // namespace mgfem
+
 static void free_ctx(mgfem_ctx* c) {
   if (!c) return;
   if (c->s) (void)hipStreamSynchronize(c->s);
   else (void)hipDeviceSynchronize();
+  for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
   for (void* q : c->allocs) (void)hipFree(q);
   if (c->red_host) (void)hipHostFree(c->red_host);
   delete c;
@@ -159,6 +190,12 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
   SETUP_TRY(ctx_alloc_t(c, &c->lam, n0));
   SETUP_TRY(ctx_alloc_t(c, &c->red_partial, 2 * kRedBlocks));
   SETUP_TRY(ctx_alloc_t(c, &c->red_out, 2));
+  SETUP_TRY(ctx_alloc_t(c, &c->sweep_counter, 1));
+  {
+    // one partial pair per level-0 sweep tile (64 x 32 tiles, or 32 x 16 below N = 1024)
+    const int64_t tiles = (int64_t)(N / 16 + 2) * (N / 16 + 2);
+    SETUP_TRY(ctx_alloc_t(c, &c->sweep_part, 2 * tiles));
+  }
   SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 2 * sizeof(double)));
   rc = setup_geometry(c, psi_dev);
   if (rc != MGFEM_OK) return bail(rc);
@@ -256,6 +293,8 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   bool conv = r0 <= rel_tol * bnorm;
   int status = MGFEM_OK;
   if (!std::isfinite(r0)) status = MGFEM_ERR_DIVERGED;
+  const bool fused = !mixed && !reverse;  // norm of u_m from the first sweep of cycle m + 1
+  bool first_done = false;
   while (status == MGFEM_OK && !conv && m < max_cycles) {
     if (mixed) {
       launch_cast_to_float(c, L0.b32, c->F64tmp, L0.n);
@@ -270,8 +309,15 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     } else {
       CycleOpts o;
       o.reverse = reverse;
+      o.first_sweep_done = first_done;
       run_cycle(c, o);
-      launch_residual_norm(c, b, L0.X[L0.cur], nullptr);
+      first_done = false;
+      if (fused && m + 1 < max_cycles) {
+        first_sweep_with_norm(c);  // leaves the iterate in place (ping-pong)
+        first_done = true;
+      } else {
+        launch_residual_norm(c, b, L0.X[L0.cur], nullptr);
+      }
     }
     MGFEM_HIP_TRY(hipGetLastError());
     double rm;
@@ -291,9 +337,13 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     prev = rm;
     conv = rm <= rel_tol * bnorm;
   }
+  // a speculative first sweep that is not followed by its cycle is discarded:
+  // the iterate is still in the buffer it read from
+  if (first_done) L0.cur = 1 - L0.cur;
   if (!mixed && L0.cur == 1) launch_copy(c, x, L0.X[1], L0.n);
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  prof_collect(c);
   L0.X[0] = nullptr;
   L0.b = nullptr;
   L0.cur = 0;
@@ -388,6 +438,36 @@ int mgfem_smooth(mgfem_handle c, int32_t level, double* x_dev, const double* b_d
   L.cur = 0;
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return MGFEM_OK;
+}
+
+int mgfem_level_counts(mgfem_handle c, int32_t level, int64_t* n_active, int64_t* n_stored,
+                       int64_t* n_cut) {
+  if (!c || level < 0 || level >= (int)c->lv.size()) return MGFEM_ERR_INVALID_ARG;
+  const Level& L = c->lv[level];
+  if (n_active) *n_active = L.n_active;
+  if (n_stored) *n_stored = L.n_stored;
+  if (n_cut) *n_cut = L.cut_off[4];
+  return MGFEM_OK;
+}
+
+int mgfem_profile(mgfem_handle c, int32_t enable) {
+  if (!c) return MGFEM_ERR_INVALID_ARG;
+  c->prof.on = enable != 0;
+  for (int k = 0; k < 4; ++k) {
+    c->prof.launches[k] = 0;
+    c->prof.ms[k] = 0.0;
+    c->prof.bytes[k] = 0.0;
+  }
+  return MGFEM_OK;
+}
+
+int mgfem_profile_read(mgfem_handle c, int32_t kernel_class, int64_t* launches, double* total_ms,
+                       double* alg_bytes) {
+  if (!c || kernel_class < 0 || kernel_class > 3) return MGFEM_ERR_INVALID_ARG;
+  if (launches) *launches = c->prof.launches[kernel_class];
+  if (total_ms) *total_ms = c->prof.ms[kernel_class];
+  if (alg_bytes) *alg_bytes = c->prof.bytes[kernel_class];
   return MGFEM_OK;
 }
 

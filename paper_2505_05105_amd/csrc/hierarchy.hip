@@ -195,6 +195,23 @@ __global__ void k_coarse_factor(const double* __restrict__ A, const uint8_t* __r
   }
 }
 
+__global__ void k_count_flags(const uint8_t* __restrict__ fl, int64_t n, unsigned long long* __restrict__ out) {
+  __shared__ unsigned int ca, cs;
+  if (threadIdx.x == 0) ca = cs = 0;
+  __syncthreads();
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n) {
+    const uint8_t f = fl[k];
+    if (f & kFlagActive) atomicAdd(&ca, 1u);
+    if ((f & kFlagActive) && (f & kFlagStored)) atomicAdd(&cs, 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (ca) atomicAdd(&out[0], (unsigned long long)ca);
+    if (cs) atomicAdd(&out[1], (unsigned long long)cs);
+  }
+}
+
 __global__ void k_to_float(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k < n) dst[k] = (float)src[k];
@@ -253,6 +270,21 @@ int setup_hierarchy(mgfem_ctx* c) {
   if (c->lv[0].empty()) {
     c->last_error = "no active node: the level set has no point with psi < 0 after snapping";
     return MGFEM_ERR_EMPTY_DOMAIN;
+  }
+  // active and stored row counts per level
+  {
+    unsigned long long* cntd = nullptr;
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &cntd, 2 * nl));
+    for (int l = 0; l < nl; ++l)
+      hipLaunchKernelGGL(k_count_flags, dim3(nblk(c->lv[l].n, tb)), dim3(tb), 0, c->s, c->lv[l].flags, c->lv[l].n,
+                         cntd + 2 * l);
+    std::vector<unsigned long long> h(2 * nl);
+    MGFEM_HIP_TRY(hipMemcpyAsync(h.data(), cntd, 2 * nl * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->s));
+    MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+    for (int l = 0; l < nl; ++l) {
+      c->lv[l].n_active = (int64_t)h[2 * l];
+      c->lv[l].n_stored = (int64_t)h[2 * l + 1];
+    }
   }
   // cut lists
   int* cnt = nullptr;

@@ -46,8 +46,29 @@ struct CutPlan {
   uint8_t* cl_own = nullptr;
   int16_t* cl_nbr = nullptr;  // 8 per closure node: <cl_cnt closure slot, >= cl_cnt external slot, -1 none
   int* ext_src = nullptr;   // >= 0 node read from x; < 0 -(1+q) read from the cut-value snapshot
+  double* cl_coef = nullptr;  // 9 per closure node: 8 off-diagonals, 1/diagonal
+  float* cl_coef32 = nullptr;
   int max_cl = 0, max_ext = 0;
+  int lds64 = 0, lds32 = 0;   // dynamic LDS of the largest group
 };
+
+// LDS layout of one cut group: values (closure, external, one zero slot),
+// right-hand sides, inverse diagonals, 8 off-diagonal coefficients per node,
+// 8 neighbour slots (int16) per node; every block 16-byte aligned.
+struct CutLds {
+  int vals, b, invd, coef, refs, total;
+};
+__host__ __device__ inline CutLds cut_lds_layout(int cl, int ext, int ts) {
+  auto a16 = [](int v) { return (v + 15) & ~15; };
+  CutLds L;
+  L.vals = 0;
+  L.b = L.vals + a16((cl + ext + 1) * ts);
+  L.invd = L.b + a16(cl * ts);
+  L.coef = L.invd + a16(cl * ts);
+  L.refs = L.coef + a16(8 * cl * ts);
+  L.total = L.refs + 16 * cl;
+  return L;
+}
 
 struct Level {
   int N = 0;
@@ -69,10 +90,25 @@ struct Level {
   float* snap32 = nullptr;
   CutPlan cp;
   int bbox[4] = {1, 0, 1, 0};  // i_lo, i_hi, j_lo, j_hi of active nodes (inclusive)
+  int64_t n_active = 0, n_stored = 0;  // active rows, rows read from the planes
+  int* tiles = nullptr;  // sweep tiles that hold an active node
+  int ntiles = 0;
+  int tile_shape = -1;
   bool empty() const { return bbox[0] > bbox[1]; }
 };
 
+// HIP-event timing of one kernel class inside a solve (see mgfem_profile)
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;  // pairs
+  std::vector<std::pair<int, double>> pending;  // (kernel class, algorithmic bytes)
+  int64_t launches[4] = {0, 0, 0, 0};
+  double ms[4] = {0, 0, 0, 0};
+  double bytes[4] = {0, 0, 0, 0};
+};
+
 // The coarsest levels run inside one workgroup, every array in LDS.
+constexpr int kDesc = 32;  // ints per coarse-level descriptor
 struct CoarsePlan {
   int lc = -1;            // first level of the single-workgroup part (-1: none)
   int* desc = nullptr;    // per level descriptor (see smoother.hip)
@@ -80,6 +116,7 @@ struct CoarsePlan {
   float* coef32 = nullptr;
   int16_t* slot = nullptr;
   int16_t* cutl = nullptr;
+  int16_t* actl = nullptr;  // active nodes per level and colour, as LDS-box indices
   double* inv = nullptr;  // inverse of the coarsest active block (float64)
   int ndesc = 0;
   int lds64 = 0, lds32 = 0;
@@ -123,9 +160,12 @@ struct mgfem_ctx {
   double* red_partial = nullptr;  // 2 * kRedBlocks
   double* red_out = nullptr;      // 2 doubles on device
   double* red_host = nullptr;     // pinned, 2 doubles
+  double* sweep_part = nullptr;   // per-tile partials of the fused residual norm
+  unsigned int* sweep_counter = nullptr;
   mgfem::Stats* stats = nullptr;  // device
   mgfem_info info{};
   std::vector<void*> allocs;
+  mgfem::Profiler prof;
   std::string last_error;
   bool batched_member = false;
 };
@@ -160,15 +200,32 @@ void launch_zero_f(mgfem_ctx* c, float* p, int64_t n);
 void launch_u8_to_f64(mgfem_ctx* c, const uint8_t* s, double* d, int64_t n);
 
 struct CycleOpts {
-  bool reverse = false;  // transposed cycle (adjoint)
-  bool fp32 = false;     // float inner cycle
+  bool reverse = false;           // transposed cycle (adjoint)
+  bool fp32 = false;              // float inner cycle
+  bool first_sweep_done = false;  // the first level-0 sweep already ran (first_sweep_with_norm)
 };
+// first pre-smoothing sweep of level 0 (float64, forward) that also reduces the
+// residual norm of its incoming iterate into red_out
+void first_sweep_with_norm(mgfem_ctx* c);
 // one cycle on level 0 from its current iterate X[cur] and right-hand side b
 void run_cycle(mgfem_ctx* c, const CycleOpts& o);
 void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32);
 void gather_snap(mgfem_ctx* c, int l, bool fp32);
 int build_plans(mgfem_ctx* c);  // cut groups and the coarse single-workgroup layout
+int build_tile_lists(mgfem_ctx* c);
+// sweep tile shapes: 64 x 64 (512 threads) on the finest level when it is
+// large, 64 x 32 on levels with N >= 1024, 32 x 16 below
+constexpr int kShapeFinest = 0, kShapeLarge = 1, kShapeSmall = 2;
+inline int sweep_shape(const mgfem_ctx* c, int l) {
+  const int N = c->lv[l].N;
+  if (l == 0 && N >= 2048) return kShapeFinest;
+  return N >= 1024 ? kShapeLarge : kShapeSmall;
+}
 void set_kernel_attributes();
+// profiling: bracket a launch (returns the event pair index or -1) and collect
+int prof_begin(mgfem_ctx* c, int kernel_class, double bytes);
+void prof_end(mgfem_ctx* c, int slot);
+void prof_collect(mgfem_ctx* c);
 
 }  // namespace mgfem
 

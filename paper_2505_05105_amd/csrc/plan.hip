@@ -19,13 +19,28 @@
 namespace mgfem {
 namespace {
 
-constexpr int kDescLen = 24;
-
 inline int align16(int v) { return (v + 15) & ~15; }
 
 __global__ void k_cutpos(const int* __restrict__ list, int cnt, int* __restrict__ pos) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < cnt) pos[list[q]] = q;
+}
+
+// closure-node coefficients in one contiguous record: 8 off-diagonals, 1/diagonal
+__global__ void k_gather_coef(const double* __restrict__ A, int64_t n, const int* __restrict__ node, int cnt,
+                              double* __restrict__ out, float* __restrict__ out32) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= cnt) return;
+  const int64_t k = node[t];
+  const int pl[8] = {0, 1, 2, 3, 5, 6, 7, 8};
+  for (int e = 0; e < 8; ++e) {
+    const double v = A[pl[e] * n + k];
+    out[9 * (int64_t)t + e] = v;
+    if (out32) out32[9 * (int64_t)t + e] = (float)v;
+  }
+  const double d = A[4 * n + k];
+  out[9 * (int64_t)t + 8] = 1.0 / d;
+  if (out32) out32[9 * (int64_t)t + 8] = 1.0f / (float)d;
 }
 
 __global__ void k_fill_i(int* __restrict__ p, int64_t n, int v) {
@@ -37,7 +52,7 @@ struct GroupBuild {
   std::vector<int> info, node, q, ext;
   std::vector<uint8_t> own;
   std::vector<int16_t> nbr;
-  int max_cl = 0, max_ext = 0;
+  int max_cl = 0, max_ext = 0, lds64 = 0, lds32 = 0;
 };
 
 // recursively split the rectangle [x0,x1) x [y0,y1) until each closure fits
@@ -95,7 +110,7 @@ bool build_groups(const std::vector<int>& nodes, const std::unordered_map<int, i
       nbr[8 * t + e] = (int16_t)(cl.size() + idx);
     }
   }
-  const size_t bytes = cl.size() * (11 * tsize + 16) + ext.size() * tsize + 16;
+  const size_t bytes = (size_t)cut_lds_layout((int)cl.size(), (int)ext.size(), (int)tsize).total;
   if (bytes > lds_cap || cl.size() + ext.size() > 32000) {
     if (x1 - x0 <= 4 && y1 - y0 <= 4) return false;
     const int xm = (x0 + x1) / 2, ym = (y0 + y1) / 2;
@@ -132,7 +147,12 @@ bool build_groups(const std::vector<int>& nodes, const std::unordered_map<int, i
     gb.q.push_back(cl[t]);
     gb.own.push_back((i >= x0 && i < x1 && j >= y0 && j < y1) ? 1 : 0);
   }
+  // neighbours outside the grid read the zero slot after the external values
+  for (auto& r : nbr)
+    if (r < 0) r = (int16_t)(cl.size() + ext.size());
   gb.nbr.insert(gb.nbr.end(), nbr.begin(), nbr.end());
+  gb.lds64 = std::max(gb.lds64, cut_lds_layout((int)cl.size(), (int)ext.size(), 8).total);
+  gb.lds32 = std::max(gb.lds32, cut_lds_layout((int)cl.size(), (int)ext.size(), 4).total);
   gb.ext.insert(gb.ext.end(), ext.begin(), ext.end());
   gb.max_cl = std::max(gb.max_cl, (int)cl.size());
   gb.max_ext = std::max(gb.max_ext, (int)ext.size());
@@ -182,7 +202,7 @@ int build_plans(mgfem_ctx* c) {
     const int nbx = (L.N + BT) / BT, nby = nbx;
     std::vector<std::vector<int>> buckets(nbx * nby);
     for (int q = 0; q < cnt; ++q) buckets[(nodes[q] % s) / BT + ((nodes[q] / s) / BT) * nbx].push_back(q);
-    const int GT = 32;
+    const int GT = 32;  // owned tile of one group
     const int ngx = (L.N + GT) / GT;
     std::vector<std::vector<int>> owned(ngx * ngx);
     for (int q = 0; q < cnt; ++q) owned[(nodes[q] % s) / GT + ((nodes[q] / s) / GT) * ngx].push_back(q);
@@ -199,6 +219,8 @@ int build_plans(mgfem_ctx* c) {
     L.cp.ngroups = (int)gb.info.size() / 9;
     L.cp.max_cl = gb.max_cl;
     L.cp.max_ext = gb.max_ext;
+    L.cp.lds64 = gb.lds64;
+    L.cp.lds32 = gb.lds32;
     int rc;
     if ((rc = upload(c, &L.cp.g_info, gb.info))) return rc;
     if ((rc = upload(c, &L.cp.cl_node, gb.node))) return rc;
@@ -206,23 +228,26 @@ int build_plans(mgfem_ctx* c) {
     if ((rc = upload(c, &L.cp.cl_own, gb.own))) return rc;
     if ((rc = upload(c, &L.cp.cl_nbr, gb.nbr))) return rc;
     if ((rc = upload(c, &L.cp.ext_src, gb.ext))) return rc;
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.cp.cl_coef, 9 * std::max<size_t>(1, gb.node.size())));
+    if (mixed) MGFEM_HIP_TRY(ctx_alloc_t(c, &L.cp.cl_coef32, 9 * std::max<size_t>(1, gb.node.size())));
+    if (!gb.node.empty())
+      hipLaunchKernelGGL(k_gather_coef, dim3((unsigned)((gb.node.size() + 255) / 256)), dim3(256), 0, c->s, L.A,
+                         L.n, L.cp.cl_node, (int)gb.node.size(), L.cp.cl_coef, L.cp.cl_coef32);
+    MGFEM_HIP_TRY(hipGetLastError());
     MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   }
 
   // --- single-workgroup coarse part: as many coarsest levels as fit in LDS
   struct LevHost {
-    int W, H, ox, oy, nstored, ncut;
-    std::vector<int16_t> slot;
+    int W, H, ox, oy, nstored, ncut, nact;
+    std::vector<int16_t> slot, cutl, actl;
     std::vector<double> coef;
-    std::vector<int16_t> cutl;
-    int cut_off[5];
+    int cut_off[5], act_off[5];
   };
   std::vector<LevHost> hosts;
-  int total64 = 0, total32 = 0;
-  int lc = nl - 1;
-  const int cn = 0;
-  (void)cn;
-  for (int l = nl - 1; l >= 1; --l) {
+  int total64 = 0;
+  int lc = nl;
+  for (int l = nl - 1; l >= 1 && nl - l <= 12; --l) {
     Level& L = c->lv[l];
     if (L.N > 256) break;
     LevHost h{};
@@ -235,6 +260,7 @@ int build_plans(mgfem_ctx* c) {
       h.W = h.H = 3;
     }
     const int nb = h.W * h.H;
+    if (nb > 32000) break;
     std::vector<uint8_t> fl(L.n);
     std::vector<double> A(9 * L.n);
     MGFEM_HIP_TRY(hipMemcpyAsync(fl.data(), L.flags, L.n, hipMemcpyDeviceToHost, c->s));
@@ -243,60 +269,74 @@ int build_plans(mgfem_ctx* c) {
     if (L.cut_off[4] > 0)
       MGFEM_HIP_TRY(hipMemcpyAsync(cl.data(), L.cut_list, L.cut_off[4] * sizeof(int), hipMemcpyDeviceToHost, c->s));
     MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+    const bool coarsest = l == nl - 1;
     h.slot.assign(nb, -2);
     h.nstored = 0;
+    std::vector<int16_t> bycol[4];
+    const int pl[8] = {0, 1, 2, 3, 5, 6, 7, 8};
     for (int q = 0; q < nb; ++q) {
       const int gi = h.ox + q % h.W, gj = h.oy + q / h.W;
       if (gi < 0 || gj < 0 || gi > L.N || gj > L.N) continue;
       const int64_t k = gi + (int64_t)gj * L.stride;
       const uint8_t f = fl[k];
-      if (!(f & kFlagActive)) continue;
-      // the box's outer ring is never active (bounding box grown by one)
+      if (!(f & kFlagActive)) continue;  // the outer ring of the box is never active
+      if (coarsest) bycol[0].push_back((int16_t)q);  // ascending node order (the inverse's order)
+      else bycol[(gi & 1) + 2 * (gj & 1)].push_back((int16_t)q);
       if (f & kFlagStored) {
         h.slot[q] = (int16_t)h.nstored++;
-        for (int p = 0; p < 9; ++p) h.coef.push_back(A[p * L.n + k]);
+        for (int e = 0; e < 8; ++e) h.coef.push_back(A[pl[e] * L.n + k]);
+        h.coef.push_back(A[4 * L.n + k]);
+        h.coef.push_back(1.0 / A[4 * L.n + k]);
       } else {
         h.slot[q] = -1;
       }
     }
-    const bool coarsest = l == nl - 1;
+    if (h.nstored > 32000) break;
+    h.act_off[0] = 0;
+    for (int cc = 0; cc < 4; ++cc) {
+      h.actl.insert(h.actl.end(), bycol[cc].begin(), bycol[cc].end());
+      h.act_off[cc + 1] = (int)h.actl.size();
+    }
+    h.nact = (int)h.actl.size();
     h.ncut = coarsest ? 0 : L.cut_off[4];
     for (int cc = 0; cc < 5; ++cc) h.cut_off[cc] = coarsest ? 0 : L.cut_off[cc];
     for (int q = 0; q < h.ncut; ++q) {
       const int k = cl[q], gi = k % L.stride, gj = k / L.stride;
       h.cutl.push_back((int16_t)((gi - h.ox) + (gj - h.oy) * h.W));
     }
-    if (nb > 32000 || h.nstored > 32000) break;
     auto bytes = [&](int ts) {
-      int b = 3 * align16(nb * ts) + align16(nb * 2) + align16(9 * h.nstored * ts) + align16(h.ncut * 2);
-      if (coarsest) b += align16(c->coarse_n * c->coarse_n * 8);
-      return b;
+      int bsz = 3 * align16(nb * ts) + align16(h.nact * 2) + align16(nb * 2) + align16(10 * h.nstored * ts) +
+                align16(h.ncut * 2);
+      if (coarsest) bsz += align16(c->coarse_n * c->coarse_n * 8);
+      return bsz;
     };
-    if (total64 + bytes(8) > (int)cap || total32 + bytes(4) > (int)cap) break;
+    if (coarsest && h.nact != c->coarse_n) {
+      c->last_error = "coarsest active count mismatch";
+      return MGFEM_ERR_HIP;
+    }
+    if (total64 + bytes(8) > (int)cap) break;
     total64 += bytes(8);
-    total32 += bytes(4);
     hosts.insert(hosts.begin(), h);
     lc = l;
   }
-  if (hosts.empty() || lc == nl) {
+  if (hosts.empty() || lc + (int)hosts.size() != nl) {
     c->last_error = "the coarsest grid does not fit in one workgroup's LDS";
     return MGFEM_ERR_UNSUPPORTED;
   }
-  // descriptors, LDS layout (float64 and float32 share the int layout with
-  // offsets for float64; float32 offsets are a second descriptor block)
+  // descriptors: a float64 block and a float32 block (same layout, different LDS offsets)
   CoarsePlan& P = c->cplan;
   P.lc = lc;
   P.ndesc = (int)hosts.size();
   std::vector<int> desc;
   std::vector<double> coef;
-  std::vector<int16_t> slot, cutl;
+  std::vector<int16_t> slot, cutl, actl;
   for (int pass = 0; pass < 2; ++pass) {
     const int ts = pass == 0 ? 8 : 4;
-    int off = 0, coef_off = 0, slot_off = 0, cut_off = 0;
+    int off = 0, coef_off = 0, slot_off = 0, cut_off = 0, act_off = 0;
     for (int q = 0; q < P.ndesc; ++q) {
       const LevHost& h = hosts[q];
       const int nb = h.W * h.H;
-      int d[kDescLen] = {0};
+      int d[kDesc] = {0};
       d[0] = c->lv[lc + q].N;
       d[1] = h.W;
       d[2] = h.H;
@@ -311,11 +351,12 @@ int build_plans(mgfem_ctx* c) {
       off += align16(nb * ts);
       d[14] = off;
       off += align16(nb * ts);
-      d[15] = 0;
+      d[15] = off;
+      off += align16(h.nact * 2);
       d[16] = off;
       off += align16(nb * 2);
       d[17] = off;
-      off += align16(9 * h.nstored * ts);
+      off += align16(10 * h.nstored * ts);
       d[18] = off;
       off += align16(h.ncut * 2);
       d[19] = h.nstored;
@@ -323,34 +364,21 @@ int build_plans(mgfem_ctx* c) {
         d[20] = off;
         off += align16(c->coarse_n * c->coarse_n * 8);
       }
-      desc.insert(desc.end(), d, d + kDescLen);
+      for (int cc = 0; cc < 5; ++cc) d[21 + cc] = act_off + h.act_off[cc];
+      desc.insert(desc.end(), d, d + kDesc);
       coef_off += h.nstored;
       slot_off += nb;
       cut_off += h.ncut;
+      act_off += h.nact;
       if (pass == 0) {
         coef.insert(coef.end(), h.coef.begin(), h.coef.end());
         slot.insert(slot.end(), h.slot.begin(), h.slot.end());
         cutl.insert(cutl.end(), h.cutl.begin(), h.cutl.end());
+        actl.insert(actl.end(), h.actl.begin(), h.actl.end());
       }
     }
     if (pass == 0) P.lds64 = off;
     else P.lds32 = off;
-  }
-  // coarsest active nodes as LDS-box indices, appended after both descriptor blocks
-  {
-    const LevHost& h = hosts.back();
-    Level& Lc = c->lv[nl - 1];
-    std::vector<int> idx(std::max(1, c->coarse_n));
-    MGFEM_HIP_TRY(hipMemcpyAsync(idx.data(), c->coarse_idx, c->coarse_n * sizeof(int), hipMemcpyDeviceToHost, c->s));
-    MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
-    std::vector<int16_t> cidx(c->coarse_n + 1, 0);
-    for (int r = 0; r < c->coarse_n; ++r) {
-      const int gi = idx[r] % Lc.stride, gj = idx[r] / Lc.stride;
-      cidx[r] = (int16_t)((gi - h.ox) + (gj - h.oy) * h.W);
-    }
-    const size_t nint = desc.size();
-    desc.resize(nint + (cidx.size() + 1) / 2 + 1, 0);
-    std::memcpy(desc.data() + nint, cidx.data(), cidx.size() * sizeof(int16_t));
   }
   int rc;
   if ((rc = upload(c, &P.desc, desc))) return rc;
@@ -361,9 +389,10 @@ int build_plans(mgfem_ctx* c) {
   }
   if ((rc = upload(c, &P.slot, slot))) return rc;
   if ((rc = upload(c, &P.cutl, cutl))) return rc;
+  if ((rc = upload(c, &P.actl, actl))) return rc;
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   set_kernel_attributes();
-  return MGFEM_OK;
+  return build_tile_lists(c);
 }
 
 }  // namespace mgfem

@@ -48,15 +48,23 @@ struct SweepArgs {
   int64_t n;
   int i0, j0, i1, j1;  // bounding box of active nodes
   int ntx, nty, per;   // tiles and tiles per XCD
+  const int* tiles;    // active tiles (row-major tile indices), or null for all
+  int ntiles;
   int reverse;
+  // optional residual norm of the incoming iterate (float64 only): per-tile
+  // partials, a completion counter and the final (max |r|, sum r^2)
+  double* part;
+  int norm;
+  const T* xc;  // coarse iterate to prolongate into the staged tile, or null
+  int sc;
 };
+
+__device__ inline double nanmax2(double a, double b) { return (b > a || b != b) ? b : a; }
 
 // product of the stored stencil row at node k with LDS values around q
 template <class T, int RW>
-__device__ inline T stored_row(const T* __restrict__ A, int64_t n, int64_t k, const T* su, int q, T& diag) {
-  diag = A[4 * n + k];
-  T acc = diag * su[q];
-  acc += A[k] * su[q - RW - 1];
+__device__ inline T stored_offdiag(const T* __restrict__ A, int64_t n, int64_t k, const T* su, int q) {
+  T acc = A[k] * su[q - RW - 1];
   acc += A[n + k] * su[q - RW];
   acc += A[2 * n + k] * su[q - RW + 1];
   acc += A[3 * n + k] * su[q - 1];
@@ -68,75 +76,172 @@ __device__ inline T stored_row(const T* __restrict__ A, int64_t n, int64_t k, co
 }
 
 template <class T, int RW>
-__device__ inline T q1_row(const T* su, int q, T& diag) {
-  diag = T(8) / T(3);
-  const T nb = (su[q - RW - 1] + su[q - RW] + su[q - RW + 1]) + (su[q - 1] + su[q + 1]) +
-               (su[q + RW - 1] + su[q + RW] + su[q + RW + 1]);
-  return diag * su[q] - nb / T(3);
+__device__ inline T q1_neighbours(const T* su, int q) {
+  return (su[q - RW - 1] + su[q - RW] + su[q - RW + 1]) + (su[q - 1] + su[q + 1]) +
+         (su[q + RW - 1] + su[q + RW] + su[q + RW + 1]);
 }
 
-template <class T, int TW, int TH>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs<T> a) {
-  constexpr int RW = TW + 2 * kHalo, RH = TH + 2 * kHalo;
-  constexpr int BW = RW - 2, BH = RH - 2;
-  __shared__ T su[RH * RW];
-  __shared__ T sb[BH * BW];
-  __shared__ uint8_t sf[BH * BW];
-  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
-  const int t = xcd * a.per + loc;
-  if (t >= a.ntx * a.nty) return;  // uniform for the whole block, before any barrier
-  const int tx = t % a.ntx, ty = t / a.ntx;
-  const int ox = a.i0 + tx * TW - kHalo, oy = a.j0 + ty * TH - kHalo;
-  for (int q = threadIdx.x; q < RW * RH; q += blockDim.x) {
-    const int gi = ox + q % RW, gj = oy + q / RW;
-    su[q] = (gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.xin[gi + (int64_t)gj * a.s] : T(0);
+// Gauss-Seidel value of one node: x_i = (b_i - sum_{j != i} a_ij x_j) / a_ii.
+// Interior Q1 rows (centre 8/3, neighbours -1/3) give (3 b_i + sum x_j) / 8.
+template <class T, int RW>
+__device__ inline T gs_value(const T* __restrict__ A, int64_t n, int64_t k, bool stored, const T* su, int q,
+                             T bv) {
+  if (stored) return (bv - stored_offdiag<T, RW>(A, n, k, su, q)) / A[4 * n + k];
+  return (T(3) * bv + q1_neighbours<T, RW>(su, q)) * T(0.125);
+}
+
+// One full four-colour sweep of a TW x TH tile.  Only the iterate is staged in
+// LDS (tile plus a halo of 4); each thread prefetches the flags and
+// right-hand sides of the nodes it updates in the four phases into
+// registers, so a block needs about 8 bytes of LDS per staged node and six
+// blocks fit on a CU.  A node's value is final after the phase of its colour,
+// so core nodes are written out right there.
+//  prolong: the staged iterate is x + P x_c (the coarse-grid correction is
+//           applied on the fly, so the first post-smoothing sweep needs no
+//           separate prolongation pass).
+//  norm:    before the first phase, the residual of the incoming iterate on
+//           the core is reduced into per-tile partials (max |r|, sum r^2).
+// final reduction of (max, sum) pairs in a fixed order
+__global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  __shared__ double smx[256], ssm[256];
+  double mx = 0.0, sm = 0.0;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+    mx = nanmax2(mx, part[2 * q]);
+    sm += part[2 * q + 1];
   }
-  for (int q = threadIdx.x; q < BW * BH; q += blockDim.x) {
-    const int gi = ox + 1 + q % BW, gj = oy + 1 + q / BW;
-    uint8_t f = 0;
-    T bv = T(0);
-    if (gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) {
-      const int64_t k = gi + (int64_t)gj * a.s;
-      f = a.fl[k];
-      if (f & kFlagActive) bv = a.b[k];
-    }
-    sf[q] = f;
-    sb[q] = bv;
-  }
+  smx[threadIdx.x] = mx;
+  ssm[threadIdx.x] = sm;
   __syncthreads();
-  for (int p = 0; p < 4; ++p) {
-    const int c = a.reverse ? 3 - p : p;
-    const int cx = c & 1, cy = c >> 1;
-    const int lo = p + 1;
-    const int fx = lo + ((cx - (ox + lo)) & 1), fy = lo + ((cy - (oy + lo)) & 1);
-    const int nx = (RW - 1 - p - fx + 1) / 2, ny = (RH - 1 - p - fy + 1) / 2;
-    for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) {
-      const int ri = fx + 2 * (q % nx), rj = fy + 2 * (q / nx);
-      const int bq = (ri - 1) + (rj - 1) * BW;
-      const uint8_t f = sf[bq];
-      if (!(f & kFlagActive)) continue;
-      const int sq = ri + rj * RW;
-      T diag, ax;
-      if (f & kFlagStored) {
-        const int64_t k = (ox + ri) + (int64_t)(oy + rj) * a.s;
-        ax = stored_row<T, RW>(a.A, a.n, k, su, sq, diag);
-      } else {
-        ax = q1_row<T, RW>(su, sq, diag);
-      }
-      su[sq] += (sb[bq] - ax) / diag;
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smx[threadIdx.x] = nanmax2(smx[threadIdx.x], smx[threadIdx.x + w]);
+      ssm[threadIdx.x] += ssm[threadIdx.x + w];
     }
     __syncthreads();
   }
-  for (int q = threadIdx.x; q < TW * TH; q += blockDim.x) {
-    const int ri = kHalo + q % TW, rj = kHalo + q / TW;
-    const int gi = ox + ri, gj = oy + rj;
-    if (gi > a.i1 || gj > a.j1) continue;
-    const uint8_t f = sf[(ri - 1) + (rj - 1) * BW];
-    if (!(f & kFlagActive)) continue;
-    const int64_t k = gi + (int64_t)gj * a.s;
-    const T v = su[ri + rj * RW];
-    a.xout[k] = v;
-    if (f & kFlagCut) a.snap[a.cutpos[k]] = v;
+  if (threadIdx.x == 0) {
+    out[0] = smx[0];
+    out[1] = ssm[0];
+  }
+}
+
+template <class T, int TW, int TH, int BS>
+__global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
+  constexpr int RW = TW + 2 * kHalo, RH = TH + 2 * kHalo;
+  constexpr int NU = (RW * RH + BS - 1) / BS;
+  constexpr int NXM = (RW - 1) / 2, NYM = (RH - 1) / 2;  // colour nodes per row/column, phase 0 bound
+  constexpr int NP = (NXM * NYM + BS - 1) / BS;          // phase nodes per thread
+  __shared__ T su[RH * RW];
+  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int t = xcd * a.per + loc;
+  if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
+  const int tile = a.tiles ? a.tiles[t] : t;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
+  const int ox = a.i0 + tx * TW - kHalo, oy = a.j0 + ty * TH - kHalo;
+  const int tid = threadIdx.x;
+  // this thread's nodes in each phase (LDS index, or -1), with flags and b
+  int pq[4][NP];
+  uint8_t pf[4][NP];
+  T pb[4][NP];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const int c = a.reverse ? 3 - p : p;
+    const int lo = p + 1, hix = RW - 1 - p, hiy = RH - 1 - p;
+    const int fx = lo + (((c & 1) - (ox + lo)) & 1), fy = lo + (((c >> 1) - (oy + lo)) & 1);
+    const int nxm = (hix - lo + 1) / 2, nym = (hiy - lo + 1) / 2;
+#pragma unroll
+    for (int it = 0; it < NP; ++it) {
+      const int q = tid + BS * it;
+      const int ri = fx + 2 * (q % nxm), rj = fy + 2 * (q / nxm);
+      const int gi = ox + ri, gj = oy + rj;
+      const bool ok = q < nxm * nym && ri < hix && rj < hiy && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N;
+      pq[p][it] = ok ? ri + rj * RW : -1;
+      pf[p][it] = ok ? a.fl[gi + (int64_t)gj * a.s] : 0;
+    }
+  }
+  T ru[NU];
+#pragma unroll
+  for (int it = 0; it < NU; ++it) {
+    const int q = tid + BS * it;
+    const int gi = ox + q % RW, gj = oy + q / RW;
+    const bool in = q < RW * RH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N;
+    T v = in ? a.xin[gi + (int64_t)gj * a.s] : T(0);
+    if (in && a.xc) {
+      // + P x_c: bilinear interpolation from the (up to) four coarse parents,
+      // written without branches: for an even index both parents coincide
+      const int I0 = gi >> 1, I1 = (gi + 1) >> 1, J0 = gj >> 1, J1 = (gj + 1) >> 1;
+      const int64_t r0 = (int64_t)J0 * a.sc, r1 = (int64_t)J1 * a.sc;
+      v += T(0.25) * ((a.xc[I0 + r0] + a.xc[I1 + r0]) + (a.xc[I0 + r1] + a.xc[I1 + r1]));
+    }
+    ru[it] = v;
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int it = 0; it < NP; ++it) {
+      const int q = pq[p][it];
+      T bv = T(0);
+      if (q >= 0 && (pf[p][it] & kFlagActive)) bv = a.b[(ox + q % RW) + (int64_t)(oy + q / RW) * a.s];
+      pb[p][it] = bv;
+    }
+#pragma unroll
+  for (int it = 0; it < NU; ++it) {
+    const int q = tid + BS * it;
+    if (q < RW * RH) su[q] = ru[it];
+  }
+  __syncthreads();
+  auto in_core = [&](int q) {
+    const int ri = q % RW, rj = q / RW;
+    return ri >= kHalo && ri < kHalo + TW && rj >= kHalo && rj < kHalo + TH && ox + ri <= a.i1 && oy + rj <= a.j1;
+  };
+  if (a.norm) {
+    __shared__ double smx[BS], ssm[BS];
+    double mx = 0.0, sm = 0.0;
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int it = 0; it < NP; ++it) {
+        const int q = pq[p][it];
+        if (q < 0 || !(pf[p][it] & kFlagActive) || !in_core(q)) continue;
+        const int64_t k = (ox + q % RW) + (int64_t)(oy + q / RW) * a.s;
+        T ax;
+        if (pf[p][it] & kFlagStored) ax = a.A[4 * a.n + k] * su[q] + stored_offdiag<T, RW>(a.A, a.n, k, su, q);
+        else ax = T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) / T(3);
+        const double r = (double)(pb[p][it] - ax);
+        mx = nanmax2(mx, fabs(r));
+        sm += r * r;
+      }
+    smx[tid] = mx;
+    ssm[tid] = sm;
+    __syncthreads();
+    for (int w = BS / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        smx[tid] = nanmax2(smx[tid], smx[tid + w]);
+        ssm[tid] += ssm[tid + w];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      a.part[2 * t] = smx[0];
+      a.part[2 * t + 1] = ssm[0];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+#pragma unroll
+    for (int it = 0; it < NP; ++it) {
+      const int q = pq[p][it];
+      const uint8_t f = pf[p][it];
+      if (q < 0 || !(f & kFlagActive)) continue;
+      const int64_t k = (ox + q % RW) + (int64_t)(oy + q / RW) * a.s;
+      const T v = gs_value<T, RW>(a.A, a.n, k, (f & kFlagStored) != 0, su, q, pb[p][it]);
+      su[q] = v;
+      if (in_core(q)) {
+        a.xout[k] = v;
+        if (f & kFlagCut) a.snap[a.cutpos[k]] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -149,36 +254,53 @@ struct CutArgs {
   const uint8_t* cl_own;
   const int16_t* cl_nbr;
   const int* ext_src;
+  const T* cl_coef;  // per closure node: 8 off-diagonals (planes 0,1,2,3,5,6,7,8) and 1/diagonal
   T* x;
   const T* b;
-  const T* A;
   const T* snap;
-  int64_t n;
   int eta, reverse;
 };
 
-__constant__ int kNbrPlane[8] = {0, 1, 2, 3, 5, 6, 7, 8};
+
+struct alignas(16) Refs8 {
+  int16_t r[8];
+};
 
 template <class T>
 __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int* gi = a.g_info + 9 * blockIdx.x;
   const int cl_off = gi[0], cl_cnt = gi[1], ext_off = gi[2], ext_cnt = gi[3];
-  T* sval = reinterpret_cast<T*>(smem);
-  T* sbv = sval + cl_cnt;
-  T* scoef = sbv + cl_cnt;
-  T* sext = scoef + 9 * cl_cnt;
-  int16_t* snbr = reinterpret_cast<int16_t*>(sext + ext_cnt);
+  const CutLds lay = cut_lds_layout(cl_cnt, ext_cnt, (int)sizeof(T));
+  T* vals = reinterpret_cast<T*>(smem + lay.vals);
+  T* sb = reinterpret_cast<T*>(smem + lay.b);
+  T* sinv = reinterpret_cast<T*>(smem + lay.invd);
+  T* scoef = reinterpret_cast<T*>(smem + lay.coef);
+  Refs8* srefs = reinterpret_cast<Refs8*>(smem + lay.refs);
+  const Refs8* grefs = reinterpret_cast<const Refs8*>(a.cl_nbr) + cl_off;
   for (int t = threadIdx.x; t < cl_cnt; t += blockDim.x) {
     const int64_t k = a.cl_node[cl_off + t];
-    sval[t] = a.snap[a.cl_q[cl_off + t]];
-    sbv[t] = a.b[k];
-    for (int p = 0; p < 9; ++p) scoef[9 * t + p] = a.A[p * a.n + k];
-    for (int e = 0; e < 8; ++e) snbr[8 * t + e] = a.cl_nbr[8 * (int64_t)(cl_off + t) + e];
+    const T v = a.snap[a.cl_q[cl_off + t]];
+    const T bv = a.b[k];
+    const T* cg = a.cl_coef + 9 * (int64_t)(cl_off + t);
+    T cf[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) cf[e] = cg[e];
+    const Refs8 rr = grefs[t];
+    vals[t] = v;
+    sb[t] = bv;
+    sinv[t] = cf[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) scoef[8 * t + e] = cf[e];
+    srefs[t] = rr;
   }
-  for (int t = threadIdx.x; t < ext_cnt; t += blockDim.x) {
-    const int src = a.ext_src[ext_off + t];
-    sext[t] = src >= 0 ? a.x[src] : a.snap[-(1 + src)];
+  for (int t = threadIdx.x; t <= ext_cnt; t += blockDim.x) {
+    T v = T(0);
+    if (t < ext_cnt) {
+      const int src = a.ext_src[ext_off + t];
+      v = src >= 0 ? a.x[src] : a.snap[-(1 + src)];
+    }
+    vals[cl_cnt + t] = v;
   }
   __syncthreads();
   for (int sweep = 0; sweep < a.eta; ++sweep) {
@@ -186,21 +308,20 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
       const int c = a.reverse ? 3 - p : p;
       const int lo = gi[4 + c], hi = gi[5 + c];
       for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-        const T diag = scoef[9 * t + 4];
-        T acc = sbv[t] - diag * sval[t];
-        for (int e = 0; e < 8; ++e) {
-          const int r = snbr[8 * t + e];
-          if (r < 0) continue;
-          const T v = r < cl_cnt ? sval[r] : sext[r - cl_cnt];
-          acc -= scoef[9 * t + kNbrPlane[e]] * v;
-        }
-        sval[t] += acc / diag;
+        const Refs8 rr = srefs[t];
+        T nb[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) nb[e] = vals[rr.r[e]];
+        T acc = sb[t];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc -= scoef[8 * t + e] * nb[e];
+        vals[t] = acc * sinv[t];
       }
       __syncthreads();
     }
   }
   for (int t = threadIdx.x; t < cl_cnt; t += blockDim.x)
-    if (a.cl_own[cl_off + t]) a.x[a.cl_node[cl_off + t]] = sval[t];
+    if (a.cl_own[cl_off + t]) a.x[a.cl_node[cl_off + t]] = vals[t];
 }
 
 // one colour phase over a list of nodes (used when a level has no group plan)
@@ -242,43 +363,70 @@ struct ResArgs {
   int ntx, nty, per;
 };
 
+template <class T, int RW>
+__device__ inline T row_product(const T* __restrict__ A, int64_t n, int64_t k, bool stored, const T* su, int q) {
+  if (stored) return A[4 * n + k] * su[q] + stored_offdiag<T, RW>(A, n, k, su, q);
+  return T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) / T(3);
+}
+
 template <class T, int CW, int CH>
 __global__ __launch_bounds__(256) void k_resrestrict(ResArgs<T> a) {
   constexpr int RW = 2 * CW + 1, RH = 2 * CH + 1;  // fine residual region
   constexpr int UW = RW + 2, UH = RH + 2;          // fine x region
+  constexpr int NU = (UW * UH + 255) / 256, NR = (RW * RH + 255) / 256;
   __shared__ T su[UH * UW];
   __shared__ T sr[RH * RW];
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
   const int t = xcd * a.per + loc;
   if (t >= a.ntx * a.nty) return;
+  const int tid = threadIdx.x;
   const int tx = t % a.ntx, ty = t / a.ntx;
   const int cI0 = a.I0 + tx * CW, cJ0 = a.J0 + ty * CH;
   const int fx0 = 2 * cI0 - 1, fy0 = 2 * cJ0 - 1;  // residual region origin
   const int ux0 = fx0 - 1, uy0 = fy0 - 1;
-  for (int q = threadIdx.x; q < UW * UH; q += blockDim.x) {
-    const int gi = ux0 + q % UW, gj = uy0 + q / UW;
-    su[q] = (gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.x[gi + (int64_t)gj * a.s] : T(0);
+  uint8_t rf[NR];
+  T rb[NR];
+  {
+    T ru[NU];
+#pragma unroll
+    for (int it = 0; it < NU; ++it) {
+      const int q = tid + 256 * it;
+      const int gi = ux0 + q % UW, gj = uy0 + q / UW;
+      ru[it] = (q < UW * UH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.x[gi + (int64_t)gj * a.s] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+      const int q = tid + 256 * it;
+      const int gi = fx0 + q % RW, gj = fy0 + q / RW;
+      rf[it] = (q < RW * RH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.fl[gi + (int64_t)gj * a.s] : 0;
+    }
+#pragma unroll
+    for (int it = 0; it < NR; ++it) {
+      const int q = tid + 256 * it;
+      const int gi = fx0 + q % RW, gj = fy0 + q / RW;
+      rb[it] = (rf[it] & kFlagActive) ? a.b[gi + (int64_t)gj * a.s] : T(0);
+    }
+#pragma unroll
+    for (int it = 0; it < NU; ++it) {
+      const int q = tid + 256 * it;
+      if (q < UW * UH) su[q] = ru[it];
+    }
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < RW * RH; q += blockDim.x) {
+#pragma unroll
+  for (int it = 0; it < NR; ++it) {
+    const int q = tid + 256 * it;
+    if (q >= RW * RH) break;
     const int ri = q % RW, rj = q / RW;
-    const int gi = fx0 + ri, gj = fy0 + rj;
     T r = T(0);
-    if (gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) {
-      const int64_t k = gi + (int64_t)gj * a.s;
-      const uint8_t f = a.fl[k];
-      if (f & kFlagActive) {
-        const int sq = (ri + 1) + (rj + 1) * UW;
-        T diag;
-        const T ax = (f & kFlagStored) ? stored_row<T, UW>(a.A, a.n, k, su, sq, diag)
-                                       : q1_row<T, UW>(su, sq, diag);
-        r = a.b[k] - ax;
-      }
+    if (rf[it] & kFlagActive) {
+      const int64_t k = (fx0 + ri) + (int64_t)(fy0 + rj) * a.s;
+      r = rb[it] - row_product<T, UW>(a.A, a.n, k, (rf[it] & kFlagStored) != 0, su, (ri + 1) + (rj + 1) * UW);
     }
     sr[q] = r;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < CW * CH; q += blockDim.x) {
+  for (int q = tid; q < CW * CH; q += 256) {
     const int I = cI0 + q % CW, J = cJ0 + q / CW;
     if (I > a.I1 || J > a.J1) continue;
     const int64_t kc = I + (int64_t)J * a.sc;
@@ -325,79 +473,119 @@ __global__ void k_snap_gather(const int* __restrict__ list, int cnt, const T* __
 }
 
 // ---------------------------------------------------------------------------
-// Coarse levels in one workgroup.  Per level the host packs a descriptor:
-//   [0] N  [1] W  [2] H  [3] ox  [4] oy  (LDS box of W x H nodes with origin
-//   (ox, oy) = bounding box grown by one ring)  [5] coef offset  [6] slot offset
-//   [7..11] cut-list offsets (5)  [12] lds offset of x  [13] of b  [14] of r
-//   [15] of flags  [16] of slot  [17] of coef  [18] of cut lists  [19] nstored
-// All LDS offsets are in bytes from the dynamic LDS base; the coarsest level
-// also holds the inverse of its active block after its coefficient block.
+// Coarse levels in one workgroup.  Per level the host packs a descriptor of
+// kDesc ints:
+//   [0] N  [1] W  [2] H  [3] ox  [4] oy   LDS box: the bounding box grown by
+//        one ring, W x H nodes with grid origin (ox, oy)
+//   [5] first stored row in the global coefficient array (10 values per row:
+//       8 off-diagonals in plane order 0,1,2,3,5,6,7,8, diagonal, 1/diagonal)
+//   [6] first box node in the global slot array
+//   [7..11] colour offsets of the cut list in the global cut-list array
+//   [12..18] LDS byte offsets of x, b, r, active lists, slots, coefficients,
+//            cut lists  [19] stored rows  [20] LDS offset of the coarsest inverse
+//   [21..25] colour offsets of the active list in the global active-list array
 // ---------------------------------------------------------------------------
-constexpr int kDesc = 24;
-
 template <class T>
 struct CoarseArgs {
-  const int* desc;     // kDesc ints per coarse level
-  const T* coef;       // compact stored stencils (9 per stored node)
-  const int16_t* slot; // per LDS-box node: stored slot, -1 regular, -2 inactive
-  const int16_t* cutl; // cut lists in LDS-box indices
-  const double* inv;   // coarsest inverse (cn x cn)
-  const int16_t* cidx; // coarsest active nodes in LDS-box indices
+  const int* desc;
+  const T* coef;
+  const int16_t* slot;  // per box node: stored row, -1 interior Q1 row, -2 inactive
+  const int16_t* cutl;
+  const int16_t* actl;
+  const double* inv;    // inverse of the coarsest active block
+  const int16_t* cidx;  // coarsest active nodes as box indices
   int cn;
-  int nlev;            // coarse levels handled here (the last one is solved exactly)
-  const T* b_top;      // right-hand side of the first coarse level (global)
-  T* x_top;            // its solution (global)
-  int s_top;           // grid stride of the first coarse level
+  int nlev;
+  const T* b_top;
+  T* x_top;
+  int s_top;
   int nu1, nu2, eta, reverse, gstar;
 };
 
+// pointers of one coarse level inside the LDS block
 template <class T>
-__device__ inline T lds_row(const int* d, const unsigned char* base, int q, T& diag) {
-  const int W = d[1];
-  const T* x = reinterpret_cast<const T*>(base + d[12]);
-  const int16_t sl = reinterpret_cast<const int16_t*>(base + d[16])[q];
-  if (sl >= 0) {
-    const T* cf = reinterpret_cast<const T*>(base + d[17]) + 9 * sl;
-    diag = cf[4];
-    return cf[0] * x[q - W - 1] + cf[1] * x[q - W] + cf[2] * x[q - W + 1] + cf[3] * x[q - 1] +
-           cf[4] * x[q] + cf[5] * x[q + 1] + cf[6] * x[q + W - 1] + cf[7] * x[q + W] +
-           cf[8] * x[q + W + 1];
+struct WgLev {
+  int W, H, ox, oy;
+  T* x;
+  T* b;
+  T* r;
+  const int16_t* act;
+  const int16_t* slot;
+  const T* coef;
+  const int16_t* cut;
+  int act_off[5], cut_off[5];
+  const double* inv;
+};
+
+template <class T>
+__device__ inline WgLev<T> wg_level(const int* d, unsigned char* base) {
+  WgLev<T> L;
+  L.W = d[1];
+  L.H = d[2];
+  L.ox = d[3];
+  L.oy = d[4];
+  L.x = reinterpret_cast<T*>(base + d[12]);
+  L.b = reinterpret_cast<T*>(base + d[13]);
+  L.r = reinterpret_cast<T*>(base + d[14]);
+  L.act = reinterpret_cast<const int16_t*>(base + d[15]);
+  L.slot = reinterpret_cast<const int16_t*>(base + d[16]);
+  L.coef = reinterpret_cast<const T*>(base + d[17]);
+  L.cut = reinterpret_cast<const int16_t*>(base + d[18]);
+  for (int c = 0; c < 5; ++c) {
+    L.act_off[c] = d[21 + c] - d[21];
+    L.cut_off[c] = d[7 + c] - d[7];
   }
-  diag = T(8) / T(3);
-  const T nb = (x[q - W - 1] + x[q - W] + x[q - W + 1]) + (x[q - 1] + x[q + 1]) +
-               (x[q + W - 1] + x[q + W] + x[q + W + 1]);
-  return diag * x[q] - nb / T(3);
+  L.inv = reinterpret_cast<const double*>(base + d[20]);
+  return L;
 }
 
 template <class T>
-__device__ void wg_smooth(const int* d, unsigned char* base, int eta, bool reverse) {
-  const int W = d[1], H = d[2];
-  T* x = reinterpret_cast<T*>(base + d[12]);
-  const T* b = reinterpret_cast<const T*>(base + d[13]);
-  const int16_t* sl = reinterpret_cast<const int16_t*>(base + d[16]);
-  const int16_t* cl = reinterpret_cast<const int16_t*>(base + d[18]);
-  const int ox = d[3], oy = d[4];
+__device__ inline T lds_gs(const WgLev<T>& L, int q) {
+  const int W = L.W;
+  const T* x = L.x;
+  const T bv = L.b[q];
+  const int16_t sl = L.slot[q];
+  if (sl >= 0) {
+    const T* cf = L.coef + 10 * sl;
+    const T acc = bv - (cf[0] * x[q - W - 1] + cf[1] * x[q - W] + cf[2] * x[q - W + 1] + cf[3] * x[q - 1] +
+                        cf[4] * x[q + 1] + cf[5] * x[q + W - 1] + cf[6] * x[q + W] + cf[7] * x[q + W + 1]);
+    return acc * cf[9];
+  }
+  const T nb = (x[q - W - 1] + x[q - W] + x[q - W + 1]) + (x[q - 1] + x[q + 1]) +
+               (x[q + W - 1] + x[q + W] + x[q + W + 1]);
+  return (T(3) * bv + nb) * T(0.125);
+}
+
+template <class T>
+__device__ inline T lds_res(const WgLev<T>& L, int q) {
+  const int W = L.W;
+  const T* x = L.x;
+  const T bv = L.b[q];
+  const int16_t sl = L.slot[q];
+  if (sl >= 0) {
+    const T* cf = L.coef + 10 * sl;
+    return bv - (cf[8] * x[q] + cf[0] * x[q - W - 1] + cf[1] * x[q - W] + cf[2] * x[q - W + 1] +
+                 cf[3] * x[q - 1] + cf[4] * x[q + 1] + cf[5] * x[q + W - 1] + cf[6] * x[q + W] +
+                 cf[7] * x[q + W + 1]);
+  }
+  const T nb = (x[q - W - 1] + x[q - W] + x[q - W + 1]) + (x[q - 1] + x[q + 1]) +
+               (x[q + W - 1] + x[q + W] + x[q + W + 1]);
+  return bv - (T(8) / T(3) * x[q] - nb / T(3));
+}
+
+template <class T>
+__device__ void wg_smooth(const WgLev<T>& L, int eta, bool reverse) {
   auto full = [&](int c) {
-    const int cx = c & 1, cy = c >> 1;
-    const int fx = 1 + ((cx - (ox + 1)) & 1), fy = 1 + ((cy - (oy + 1)) & 1);
-    const int nx = (W - 1 - fx + 1) / 2, ny = (H - 1 - fy + 1) / 2;
-    for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) {
-      const int li = fx + 2 * (q % nx), lj = fy + 2 * (q / nx);
-      const int qq = li + lj * W;
-      if (sl[qq] == -2) continue;
-      T diag;
-      const T ax = lds_row<T>(d, base, qq, diag);
-      x[qq] += (b[qq] - ax) / diag;
+    for (int t = L.act_off[c] + threadIdx.x; t < L.act_off[c + 1]; t += blockDim.x) {
+      const int q = L.act[t];
+      L.x[q] = lds_gs<T>(L, q);
     }
     __syncthreads();
   };
   auto cut = [&](int c) {
-    const int lo = d[7 + c] - d[7], hi = d[8 + c] - d[7];
-    for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-      const int qq = cl[t];
-      T diag;
-      const T ax = lds_row<T>(d, base, qq, diag);
-      x[qq] += (b[qq] - ax) / diag;
+    for (int t = L.cut_off[c] + threadIdx.x; t < L.cut_off[c + 1]; t += blockDim.x) {
+      const int q = L.cut[t];
+      L.x[q] = lds_gs<T>(L, q);
     }
     __syncthreads();
   };
@@ -412,118 +600,135 @@ __device__ void wg_smooth(const int* d, unsigned char* base, int eta, bool rever
   }
 }
 
-// restriction of the residual of level d (fine) to level dc (coarse), in LDS
+// residual of level F restricted to level C (weights 1, 1/2, 1/4); x_C = 0
 template <class T>
-__device__ void wg_restrict(const int* d, const int* dc, unsigned char* base) {
-  const int W = d[1], H = d[2];
-  T* r = reinterpret_cast<T*>(base + d[14]);
-  const T* b = reinterpret_cast<const T*>(base + d[13]);
-  const int16_t* sl = reinterpret_cast<const int16_t*>(base + d[16]);
-  for (int q = threadIdx.x; q < W * H; q += blockDim.x) {
-    const int li = q % W, lj = q / W;
-    T rv = T(0);
-    if (li > 0 && lj > 0 && li < W - 1 && lj < H - 1 && sl[q] != -2) {
-      T diag;
-      rv = b[q] - lds_row<T>(d, base, q, diag);
-    }
-    r[q] = rv;
+__device__ void wg_restrict(const WgLev<T>& F, const WgLev<T>& C) {
+  const int na = F.act_off[4];
+  for (int t = threadIdx.x; t < na; t += blockDim.x) {
+    const int q = F.act[t];
+    F.r[q] = lds_res<T>(F, q);
   }
   __syncthreads();
-  const int Wc = dc[1], Hc = dc[2];
-  T* xc = reinterpret_cast<T*>(base + dc[12]);
-  T* bc = reinterpret_cast<T*>(base + dc[13]);
-  const int16_t* slc = reinterpret_cast<const int16_t*>(base + dc[16]);
-  for (int q = threadIdx.x; q < Wc * Hc; q += blockDim.x) {
-    xc[q] = T(0);
+  const int nac = C.act_off[4];
+  for (int t = threadIdx.x; t < nac; t += blockDim.x) {
+    const int q = C.act[t];
+    const int I = C.ox + q % C.W, J = C.oy + q / C.W;
+    const int fi = 2 * I - F.ox, fj = 2 * J - F.oy;  // centre in the fine box
     T v = T(0);
-    if (slc[q] != -2) {
-      const int I = dc[3] + q % Wc, J = dc[4] + q / Wc;
-      const int fi = 2 * I - d[3], fj = 2 * J - d[4];  // centre in the fine LDS box
-      for (int dj = -1; dj <= 1; ++dj)
-        for (int di = -1; di <= 1; ++di) {
-          const int li = fi + di, lj = fj + dj;
-          if (li < 0 || lj < 0 || li >= W || lj >= H) continue;
-          const T w = T((di == 0 ? 1.0 : 0.5) * (dj == 0 ? 1.0 : 0.5));
-          v += w * r[li + lj * W];
-        }
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int lj = fj + dj;
+      if (lj < 0 || lj >= F.H) continue;
+      const T wj = dj == 0 ? T(1) : T(0.5);
+      const T* rr = F.r + lj * F.W;
+      const T row = (fi >= 0 && fi < F.W) ? rr[fi] : T(0);
+      T side = T(0);
+      if (fi - 1 >= 0 && fi - 1 < F.W) side += rr[fi - 1];
+      if (fi + 1 >= 0 && fi + 1 < F.W) side += rr[fi + 1];
+      v += wj * (row + T(0.5) * side);
     }
-    bc[q] = v;
+    C.b[q] = v;
+    C.x[q] = T(0);
   }
   __syncthreads();
 }
 
 template <class T>
-__device__ void wg_prolong(const int* d, const int* dc, unsigned char* base) {
-  const int W = d[1], H = d[2];
-  T* x = reinterpret_cast<T*>(base + d[12]);
-  const int16_t* sl = reinterpret_cast<const int16_t*>(base + d[16]);
-  const int Wc = dc[1];
-  const T* xc = reinterpret_cast<const T*>(base + dc[12]);
-  for (int q = threadIdx.x; q < W * H; q += blockDim.x) {
-    if (sl[q] == -2) continue;
-    const int i = d[3] + q % W, j = d[4] + q / W;
-    const int I = (i >> 1) - dc[3], J = (j >> 1) - dc[4];
-    const int kc = I + J * Wc;
+__device__ void wg_prolong(const WgLev<T>& F, const WgLev<T>& C) {
+  const int na = F.act_off[4];
+  const int Wc = C.W;
+  for (int t = threadIdx.x; t < na; t += blockDim.x) {
+    const int q = F.act[t];
+    const int i = F.ox + q % F.W, j = F.oy + q / F.W;
+    const int kc = ((i >> 1) - C.ox) + ((j >> 1) - C.oy) * Wc;
+    const T* xc = C.x;
     T val;
     if (!(i & 1) && !(j & 1)) val = xc[kc];
     else if ((i & 1) && !(j & 1)) val = T(0.5) * (xc[kc] + xc[kc + 1]);
     else if (!(i & 1) && (j & 1)) val = T(0.5) * (xc[kc] + xc[kc + Wc]);
     else val = T(0.25) * ((xc[kc] + xc[kc + 1]) + (xc[kc + Wc] + xc[kc + Wc + 1]));
-    x[q] += val;
+    F.x[q] += val;
   }
   __syncthreads();
 }
 
+constexpr int kMaxWgLevels = 12;
+
+// One cycle from the first coarse level, written without recursion (a
+// recursive device function would keep its frames in scratch memory).  The
+// counters of coarse-grid visits (gamma* per level) live in a 64-bit word.
 template <class T>
-__device__ void wg_cycle(const CoarseArgs<T>& a, unsigned char* base, int l) {
-  const int* d = a.desc + kDesc * l;
-  if (l == a.nlev - 1) {  // exact solve with the stored inverse (float64)
-    T* x = reinterpret_cast<T*>(base + d[12]);
-    const T* b = reinterpret_cast<const T*>(base + d[13]);
-    const double* inv = reinterpret_cast<const double*>(base + d[20]);
-    for (int r = threadIdx.x; r < a.cn; r += blockDim.x) {
-      double acc = 0.0;
-      for (int cc = 0; cc < a.cn; ++cc) acc += inv[r * a.cn + cc] * (double)b[a.cidx[cc]];
-      x[a.cidx[r]] = (T)acc;
-    }
-    __syncthreads();
-    return;
-  }
-  const int* dc = a.desc + kDesc * (l + 1);
+__device__ void wg_cycle(const CoarseArgs<T>& a, const int* sdesc, unsigned char* base) {
+  const int last = a.nlev - 1;
   const int pre = a.reverse ? a.nu2 : a.nu1, post = a.reverse ? a.nu1 : a.nu2;
-  for (int s = 0; s < pre; ++s) wg_smooth<T>(d, base, a.eta, a.reverse);
-  wg_restrict<T>(d, dc, base);
-  for (int g = 0; g < a.gstar; ++g) wg_cycle<T>(a, base, l + 1);
-  wg_prolong<T>(d, dc, base);
-  for (int s = 0; s < post; ++s) wg_smooth<T>(d, base, a.eta, a.reverse);
+  unsigned long long visits = 0;  // 4 bits per level
+  int l = 0;
+  bool enter = true;
+  while (l >= 0) {
+    if (enter) {
+      const WgLev<T> L = wg_level<T>(sdesc + kDesc * l, base);
+      if (l == last) {  // exact solve with the stored inverse (float64)
+        for (int r = threadIdx.x; r < a.cn; r += blockDim.x) {
+          double acc = 0.0;
+          for (int cc = 0; cc < a.cn; ++cc) acc += L.inv[r * a.cn + cc] * (double)L.b[L.act[cc]];
+          L.x[L.act[r]] = (T)acc;
+        }
+        __syncthreads();
+        enter = false;
+        --l;
+        continue;
+      }
+      const WgLev<T> C = wg_level<T>(sdesc + kDesc * (l + 1), base);
+      for (int s = 0; s < pre; ++s) wg_smooth<T>(L, a.eta, a.reverse);
+      wg_restrict<T>(L, C);
+      visits &= ~(0xfull << (4 * l));
+      ++l;
+      continue;
+    }
+    const unsigned long long g = ((visits >> (4 * l)) & 0xf) + 1;
+    visits = (visits & ~(0xfull << (4 * l))) | (g << (4 * l));
+    if ((int)g < a.gstar) {  // another coarse-grid cycle from the current iterate
+      ++l;
+      enter = true;
+      continue;
+    }
+    const WgLev<T> L = wg_level<T>(sdesc + kDesc * l, base);
+    const WgLev<T> C = wg_level<T>(sdesc + kDesc * (l + 1), base);
+    wg_prolong<T>(L, C);
+    for (int s = 0; s < post; ++s) wg_smooth<T>(L, a.eta, a.reverse);
+    --l;
+  }
 }
 
 template <class T>
 __global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
   extern __shared__ __align__(16) unsigned char base[];
-  // stage every coarse level: x = 0, b = 0 (b of the first level from global),
-  // flags/slots, stored stencils, cut lists; the inverse of the coarsest block
+  __shared__ int sdesc[kDesc * kMaxWgLevels];
+  for (int q = threadIdx.x; q < kDesc * a.nlev; q += blockDim.x) sdesc[q] = a.desc[q];
   for (int l = 0; l < a.nlev; ++l) {
     const int* d = a.desc + kDesc * l;
     const int W = d[1], H = d[2], nb = W * H;
     T* x = reinterpret_cast<T*>(base + d[12]);
     T* b = reinterpret_cast<T*>(base + d[13]);
+    T* r = reinterpret_cast<T*>(base + d[14]);
     int16_t* sl = reinterpret_cast<int16_t*>(base + d[16]);
     T* cf = reinterpret_cast<T*>(base + d[17]);
     int16_t* cl = reinterpret_cast<int16_t*>(base + d[18]);
+    int16_t* act = reinterpret_cast<int16_t*>(base + d[15]);
     for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+      const int16_t s = a.slot[d[6] + q];
       x[q] = T(0);
-      sl[q] = a.slot[d[6] + q];
+      r[q] = T(0);
+      sl[q] = s;
       T bv = T(0);
-      if (l == 0 && sl[q] != -2) {
+      if (l == 0 && s != -2) {
         const int gi = d[3] + q % W, gj = d[4] + q / W;
         bv = a.b_top[gi + (int64_t)gj * a.s_top];
       }
       b[q] = bv;
     }
-    for (int q = threadIdx.x; q < 9 * d[19]; q += blockDim.x) cf[q] = a.coef[9 * (int64_t)d[5] + q];
-    const int ncl = d[11] - d[7];
-    for (int q = threadIdx.x; q < ncl; q += blockDim.x) cl[q] = a.cutl[d[7] + q];
+    for (int q = threadIdx.x; q < 10 * d[19]; q += blockDim.x) cf[q] = a.coef[10 * (int64_t)d[5] + q];
+    for (int q = threadIdx.x; q < d[11] - d[7]; q += blockDim.x) cl[q] = a.cutl[d[7] + q];
+    for (int q = threadIdx.x; q < d[25] - d[21]; q += blockDim.x) act[q] = a.actl[d[21] + q];
     if (l == a.nlev - 1) {
       double* inv = reinterpret_cast<double*>(base + d[20]);
       for (int q = threadIdx.x; q < a.cn * a.cn; q += blockDim.x) inv[q] = a.inv[q];
@@ -531,15 +736,12 @@ __global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
   }
   __syncthreads();
   // gamma* cycles on the first coarse level, each continuing from the last
-  for (int g = 0; g < a.gstar; ++g) wg_cycle<T>(a, base, 0);
-  const int* d = a.desc;
-  const int W = d[1], H = d[2];
-  const T* x = reinterpret_cast<const T*>(base + d[12]);
-  const int16_t* sl = reinterpret_cast<const int16_t*>(base + d[16]);
-  for (int q = threadIdx.x; q < W * H; q += blockDim.x) {
-    if (sl[q] == -2) continue;
-    const int gi = d[3] + q % W, gj = d[4] + q / W;
-    a.x_top[gi + (int64_t)gj * a.s_top] = x[q];
+  for (int g = 0; g < a.gstar; ++g) wg_cycle<T>(a, sdesc, base);
+  const WgLev<T> L = wg_level<T>(sdesc, base);
+  for (int t = threadIdx.x; t < L.act_off[4]; t += blockDim.x) {
+    const int q = L.act[t];
+    const int gi = L.ox + q % L.W, gj = L.oy + q / L.W;
+    a.x_top[gi + (int64_t)gj * a.s_top] = L.x[q];
   }
 }
 
@@ -570,10 +772,19 @@ double* Sp<double>(Level& L) { return L.snap; }
 template <>
 float* Sp<float>(Level& L) { return L.snap32; }
 
-template <class T, int TW, int TH>
-void launch_sweep(mgfem_ctx* c, int l, bool reverse) {
+template <class T, int TW, int TH, int BS>
+void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_from, int shape) {
   Level& L = c->lv[l];
   SweepArgs<T> a;
+  a.part = c->sweep_part;
+  a.norm = norm ? 1 : 0;
+  a.xc = nullptr;
+  a.sc = 0;
+  if (prolong_from) {
+    Level& C = c->lv[l + 1];
+    a.xc = Xp<T>(C, C.cur);
+    a.sc = C.stride;
+  }
   a.xin = Xp<T>(L, L.cur);
   a.xout = Xp<T>(L, 1 - L.cur);
   a.b = Bp<T>(L);
@@ -590,19 +801,39 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse) {
   a.j1 = L.bbox[3];
   a.ntx = (a.i1 - a.i0 + TW) / TW;
   a.nty = (a.j1 - a.j0 + TH) / TH;
-  const int tiles = a.ntx * a.nty;
-  a.per = (tiles + 7) / 8;
+  a.tiles = nullptr;
+  a.ntiles = a.ntx * a.nty;
+  if (L.tile_shape == shape && L.tiles) {
+    a.tiles = L.tiles;
+    a.ntiles = L.ntiles;
+  }
+  a.per = (a.ntiles + 7) / 8;
   a.reverse = reverse ? 1 : 0;
-  hipLaunchKernelGGL((k_sweep<T, TW, TH>), dim3(8 * a.per), dim3(256), 0, c->s, a);
+  int slot = -1;
+  if (c->prof.on && std::is_same<T, double>::value && l == 0) {
+    // algorithmic bytes: per active row x read and written, b read, its flag,
+    // the 72 bytes of a stored row; a fused prolongation also reads x_c
+    double bytes = 25.0 * L.n_active + 72.0 * L.n_stored;
+    if (prolong_from) bytes += 8.0 * c->lv[l + 1].n_active;
+    slot = prof_begin(c, 0, bytes);
+  }
+  hipLaunchKernelGGL((k_sweep<T, TW, TH, BS>), dim3(8 * a.per), dim3(BS), 0, c->s, a);
+  if (slot >= 0) prof_end(c, slot);
+  if (norm)
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, c->s, (const double*)c->sweep_part, a.ntiles,
+                       c->red_out);
   L.cur = 1 - L.cur;
 }
 
 template <class T>
-void sweep(mgfem_ctx* c, int l, bool reverse) {
+void sweep(mgfem_ctx* c, int l, bool reverse, bool norm = false, bool prolong_from = false) {
   Level& L = c->lv[l];
   if (L.empty()) return;
-  if (L.N >= 1024) launch_sweep<T, 64, 32>(c, l, reverse);
-  else launch_sweep<T, 32, 16>(c, l, reverse);
+  switch (sweep_shape(c, l)) {
+    case kShapeFinest: launch_sweep<T, 64, 64, 512>(c, l, reverse, norm, prolong_from, kShapeFinest); break;
+    case kShapeLarge: launch_sweep<T, 64, 32, 256>(c, l, reverse, norm, prolong_from, kShapeLarge); break;
+    default: launch_sweep<T, 32, 16, 256>(c, l, reverse, norm, prolong_from, kShapeSmall); break;
+  }
 }
 
 template <class T>
@@ -618,14 +849,14 @@ void cut_sweeps(mgfem_ctx* c, int l, bool reverse) {
     a.cl_own = L.cp.cl_own;
     a.cl_nbr = L.cp.cl_nbr;
     a.ext_src = L.cp.ext_src;
+    a.cl_coef = std::is_same<T, double>::value ? reinterpret_cast<const T*>(L.cp.cl_coef)
+                                               : reinterpret_cast<const T*>(L.cp.cl_coef32);
     a.x = Xp<T>(L, L.cur);
     a.b = Bp<T>(L);
-    a.A = Ap<T>(L);
     a.snap = Sp<T>(L);
-    a.n = L.n;
     a.eta = eta;
     a.reverse = reverse ? 1 : 0;
-    const size_t lds = (size_t)L.cp.max_cl * (11 * sizeof(T) + 16) + (size_t)L.cp.max_ext * sizeof(T) + 16;
+    const size_t lds = std::is_same<T, double>::value ? L.cp.lds64 : L.cp.lds32;
     hipLaunchKernelGGL(k_cut<T>, dim3(L.cp.ngroups), dim3(256), lds, c->s, a);
     return;
   }
@@ -702,8 +933,9 @@ void coarse_wg(mgfem_ctx* c, bool reverse) {
                                           : reinterpret_cast<const T*>(P.coef32);
   a.slot = P.slot;
   a.cutl = P.cutl;
+  a.actl = P.actl;
   a.inv = P.inv;
-  a.cidx = reinterpret_cast<const int16_t*>(P.desc + 2 * kDesc * P.ndesc);
+  a.cidx = nullptr;
   a.cn = c->coarse_n;
   a.nlev = P.ndesc;
   a.b_top = Bp<T>(Lc);
@@ -720,7 +952,7 @@ void coarse_wg(mgfem_ctx* c, bool reverse) {
 }
 
 template <class T>
-void cycle_level(mgfem_ctx* c, int l, bool reverse) {
+void cycle_level(mgfem_ctx* c, int l, bool reverse, bool first_sweep_done = false) {
   const int nl = (int)c->lv.size();
   if (c->cplan.lc >= 0 && l == c->cplan.lc) {
     coarse_wg<T>(c, reverse);
@@ -729,22 +961,77 @@ void cycle_level(mgfem_ctx* c, int l, bool reverse) {
   if (l == nl - 1) return;  // unreachable: the coarse plan always covers the coarsest level
   const int pre = reverse ? c->p.nu2 : c->p.nu1;
   const int post = reverse ? c->p.nu1 : c->p.nu2;
-  for (int s = 0; s < pre; ++s) smooth<T>(c, l, reverse);
+  for (int s = 0; s < pre; ++s) {
+    if (s == 0 && first_sweep_done) cut_sweeps<T>(c, l, reverse);
+    else smooth<T>(c, l, reverse);
+  }
   if (c->lv[l].N >= 1024) launch_resrestrict<T, 32, 16>(c, l);
   else launch_resrestrict<T, 16, 8>(c, l);
   const int gstar = c->p.cycle == MGFEM_CYCLE_W ? 2 : 1;
   if (l + 1 == c->cplan.lc) coarse_wg<T>(c, reverse);  // runs its gamma* cycles itself
   else
     for (int g = 0; g < gstar; ++g) cycle_level<T>(c, l + 1, reverse);
-  prolong<T>(c, l);
-  for (int s = 0; s < post; ++s) smooth<T>(c, l, reverse);
+  if (reverse || post == 0) {
+    prolong<T>(c, l);
+    for (int s = 0; s < post; ++s) smooth<T>(c, l, reverse);
+  } else {
+    sweep<T>(c, l, false, false, true);  // x + P x_c, then the sweep
+    cut_sweeps<T>(c, l, false);
+    for (int s = 1; s < post; ++s) smooth<T>(c, l, reverse);
+  }
 }
 
 }  // namespace
 
 void run_cycle(mgfem_ctx* c, const CycleOpts& o) {
-  if (o.fp32) cycle_level<float>(c, 0, o.reverse);
-  else cycle_level<double>(c, 0, o.reverse);
+  if (o.fp32) cycle_level<float>(c, 0, o.reverse, o.first_sweep_done);
+  else cycle_level<double>(c, 0, o.reverse, o.first_sweep_done);
+}
+
+void first_sweep_with_norm(mgfem_ctx* c) { sweep<double>(c, 0, false, true); }
+
+// tile activity of one level for its sweep shape: a tile is kept when its core
+// holds an active node (tiles entirely outside the domain are skipped)
+__global__ void k_tile_active(const uint8_t* __restrict__ fl, int s, int i0, int j0, int i1, int j1, int TW, int TH,
+                              int ntx, int nty, int* __restrict__ act) {
+  const int t = blockIdx.x;
+  if (t >= ntx * nty) return;
+  const int x0 = i0 + (t % ntx) * TW, y0 = j0 + (t / ntx) * TH;
+  int any = 0;
+  for (int q = threadIdx.x; q < TW * TH; q += blockDim.x) {
+    const int gi = x0 + q % TW, gj = y0 + q / TW;
+    if (gi <= i1 && gj <= j1 && (fl[gi + (int64_t)gj * s] & kFlagActive)) any = 1;
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) act[t] = any;
+}
+
+int build_tile_lists(mgfem_ctx* c) {
+  for (int l = 0; l < (int)c->lv.size(); ++l) {
+    Level& L = c->lv[l];
+    if (L.empty() || (c->cplan.lc >= 0 && l >= c->cplan.lc)) continue;
+    const int shape = sweep_shape(c, l);
+    const int TW = shape == kShapeFinest ? 64 : (shape == kShapeLarge ? 64 : 32);
+    const int TH = shape == kShapeFinest ? 64 : (shape == kShapeLarge ? 32 : 16);
+    const int ntx = (L.bbox[1] - L.bbox[0] + TW) / TW, nty = (L.bbox[3] - L.bbox[2] + TH) / TH;
+    int* act = nullptr;
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &act, ntx * nty));
+    hipLaunchKernelGGL(k_tile_active, dim3(ntx * nty), dim3(256), 0, c->s, L.flags, L.stride, L.bbox[0], L.bbox[2],
+                       L.bbox[1], L.bbox[3], TW, TH, ntx, nty, act);
+    std::vector<int> h(ntx * nty);
+    MGFEM_HIP_TRY(hipMemcpyAsync(h.data(), act, h.size() * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+    std::vector<int> list;
+    for (int t = 0; t < ntx * nty; ++t)
+      if (h[t]) list.push_back(t);
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tiles, std::max<size_t>(1, list.size())));
+    if (!list.empty())
+      MGFEM_HIP_TRY(hipMemcpyAsync(L.tiles, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, c->s));
+    L.ntiles = (int)list.size();
+    L.tile_shape = shape;
+  }
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return MGFEM_OK;
 }
 
 void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32) {
