@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <chrono>
 #include <new>
 
 #include "mgfem_internal.h"
@@ -196,7 +197,8 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
     const int64_t tiles = (int64_t)(N / 16 + 2) * (N / 16 + 2);
     SETUP_TRY(ctx_alloc_t(c, &c->sweep_part, 2 * tiles));
   }
-  SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 2 * sizeof(double)));
+  SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 4 * sizeof(double)));
+  c->red_host[2] = 0.0;
   rc = setup_geometry(c, psi_dev);
   if (rc != MGFEM_OK) return bail(rc);
   rc = setup_hierarchy(c);
@@ -263,11 +265,28 @@ int mgfem_destroy(mgfem_handle h) {
 namespace {
 
 // read c->red_out (max, sum of squares) to the host
-int read_norm(mgfem_ctx* c, double& mx, double& l2) {
-  MGFEM_HIP_TRY(hipMemcpyAsync(c->red_host, c->red_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
-  mx = c->red_host[0];
-  l2 = std::sqrt(c->red_host[1]);
+int read_norm(mgfem_ctx* c, double& mx, double& l2, double* raw_sum = nullptr) {
+  // the reduction kernel writes (max, sum of squares, sequence number) into
+  // pinned host memory; wait for this reduction's number, then fall back to a
+  // stream synchronisation if it does not arrive (a failed launch)
+  volatile double* h = c->red_host;
+  const double want = c->red_seq;
+  const auto t0 = std::chrono::steady_clock::now();
+  while (h[2] != want) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
+      MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+      MGFEM_HIP_TRY(hipGetLastError());
+      if (h[2] != want) {
+        c->last_error = "residual norm " + std::to_string(want) + " did not arrive (last " +
+                        std::to_string(h[2]) + ")";
+        return MGFEM_ERR_HIP;
+      }
+      break;
+    }
+  }
+  mx = h[0];
+  l2 = std::sqrt(h[1]);
+  if (raw_sum) *raw_sum = h[1];
   return MGFEM_OK;
 }
 
@@ -412,10 +431,10 @@ int mgfem_misfit(mgfem_handle c, const double* u_dev, const double* ut_dev, doub
   launch_stencil_apply(c, c->M, e, Me, false);
   launch_dot_reduce(c, e, Me);
   MGFEM_HIP_TRY(hipGetLastError());
-  double mx, l2;
-  int rc = read_norm(c, mx, l2);
+  double mx, l2, sum;
+  int rc = read_norm(c, mx, l2, &sum);
   if (rc) return rc;
-  *J_host = 0.5 * c->red_host[1];
+  *J_host = 0.5 * sum;
   return MGFEM_OK;
 }
 

@@ -107,7 +107,8 @@ __global__ void k_dot_partial(const double* __restrict__ a, const double* __rest
   }
 }
 
-__global__ void k_reduce_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+__global__ void k_reduce_final(const double* __restrict__ part, int nb, double* __restrict__ out,
+                               double* host_out, double seq) {
   __shared__ double smax[256], ssum[256];
   double mx = 0.0, sm = 0.0;
   for (int t = threadIdx.x; t < nb; t += blockDim.x) {
@@ -127,6 +128,13 @@ __global__ void k_reduce_final(const double* __restrict__ part, int nb, double* 
   if (threadIdx.x == 0) {
     out[0] = smax[0];
     out[1] = ssum[0];
+    if (host_out) {  // straight to pinned host memory; the sequence number goes last
+      host_out[0] = smax[0];
+      host_out[1] = ssum[0];
+      __threadfence_system();
+      host_out[2] = seq;
+      __threadfence_system();
+    }
   }
 }
 
@@ -245,14 +253,18 @@ void launch_residual_norm(mgfem_ctx* c, const double* F, const double* u, double
   const int nb = (int)std::min<int64_t>(kRedBlocks, (tot + 255) / 256);
   hipLaunchKernelGGL(k_resnorm_partial, dim3(nb), dim3(256), 0, c->s, v, F, r_out, L.bbox[0],
                      L.bbox[2], ni, nj, c->red_partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out);
+  c->red_seq += 1.0;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
+                     c->red_seq);
 }
 
 void launch_dot_reduce(mgfem_ctx* c, const double* a, const double* b) {
   const int64_t n = c->lv[0].n;
   const int nb = (int)std::min<int64_t>(kRedBlocks, (n + 255) / 256);
   hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, c->s, a, b, n, c->red_partial);
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out);
+  c->red_seq += 1.0;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
+                     c->red_seq);
 }
 
 }  // namespace mgfem

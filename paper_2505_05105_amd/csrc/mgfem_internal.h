@@ -159,7 +159,8 @@ struct mgfem_ctx {
   // reductions
   double* red_partial = nullptr;  // 2 * kRedBlocks
   double* red_out = nullptr;      // 2 doubles on device
-  double* red_host = nullptr;     // pinned, 2 doubles
+  double* red_host = nullptr;     // pinned: max, sum of squares, sequence number
+  double red_seq = 0.0;           // sequence number of the last reduction launched
   double* sweep_part = nullptr;   // per-tile partials of the fused residual norm
   unsigned int* sweep_counter = nullptr;
   mgfem::Stats* stats = nullptr;  // device

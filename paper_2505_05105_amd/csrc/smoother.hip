@@ -102,7 +102,8 @@ __device__ inline T gs_value(const T* __restrict__ A, int64_t n, int64_t k, bool
 //  norm:    before the first phase, the residual of the incoming iterate on
 //           the core is reduced into per-tile partials (max |r|, sum r^2).
 // final reduction of (max, sum) pairs in a fixed order
-__global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out) {
+__global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out, double* host_out,
+                               double seq) {
   __shared__ double smx[256], ssm[256];
   double mx = 0.0, sm = 0.0;
   for (int q = threadIdx.x; q < nb; q += blockDim.x) {
@@ -122,6 +123,11 @@ __global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* 
   if (threadIdx.x == 0) {
     out[0] = smx[0];
     out[1] = ssm[0];
+    host_out[0] = smx[0];  // straight to pinned host memory; the sequence number goes last
+    host_out[1] = ssm[0];
+    __threadfence_system();
+    host_out[2] = seq;
+    __threadfence_system();
   }
 }
 
@@ -819,9 +825,11 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   }
   hipLaunchKernelGGL((k_sweep<T, TW, TH, BS>), dim3(8 * a.per), dim3(BS), 0, c->s, a);
   if (slot >= 0) prof_end(c, slot);
-  if (norm)
+  if (norm) {
+    c->red_seq += 1.0;
     hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, c->s, (const double*)c->sweep_part, a.ntiles,
-                       c->red_out);
+                       c->red_out, c->red_host, c->red_seq);
+  }
   L.cur = 1 - L.cur;
 }
 
