@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also time the adjoint and batched forms")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the solves, run a plain 512 MiB device copy (counter calibration)")
     return ap.parse_args()
@@ -100,6 +101,95 @@ def cpu_baseline(prob, N, gpu_cycles, cycles):
         "hist": [float(x) for x in res.hist],
         "cpu": _cpu_name(), "nproc": os.cpu_count(),
     }
+
+
+def bench_batched(args, mg, W, torch, dev):
+    """Batched form: `args.batch` seeded random ellipses, N drawn from
+    {64, 128, 256, 512}, f ~ U[-1, 1], g = 0, one persistent launch per solve
+    (float32 cycles with float64 refinement), against the plain float64
+    single-problem solver run over the same problems one after another."""
+    import numpy as np
+    probs = W.batched_draws(count=args.batch, seed=0)
+    psis = [torch.tensor(p.psi, device=dev) for p in probs]
+    fs = [torch.tensor(p.f, device=dev) for p in probs]
+    gs = [torch.tensor(p.g, device=dev) for p in probs]
+    Ns = [p.N for p in probs]
+    t0 = time.perf_counter()
+    bs = mg.BatchedSolver(psis, Ns)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    outs = [torch.empty((n + 1) ** 2, dtype=torch.float64, device=dev) for n in Ns]
+    for _ in range(args.warmup):
+        bs.solve(fs, gs, tol=args.tol, max_cycles=100, outs=outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, hists = bs.solve(fs, gs, tol=args.tol, max_cycles=100, outs=outs)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    dof = bs_info_dof(bs, mg)
+    cycles = [len(h) - 1 for h in hists]
+    worst = max(float(h[-1] / h[0]) for h in hists)
+    log(f"[bench] batched x{len(probs)}: {ms:.2f} ms/batch ({bs.last_ms():.2f} ms kernel), "
+        f"{dof / (ms * 1e-3) / 1e9:.3f} GDOF/s, tile {bs.tile}")
+    tile = bs.tile
+    bs.close()
+    del outs
+    # the plain float64 form on the same problems, one solve after another
+    solvers = [mg.Solver(p, n) for p, n in zip(psis, Ns)]
+    u1 = [torch.empty((n + 1) ** 2, dtype=torch.float64, device=dev) for n in Ns]
+    for s, f, g, u in zip(solvers, fs, gs, u1):
+        s.solve(f, g, tol=args.tol, max_cycles=100, out=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, f, g, u in zip(solvers, fs, gs, u1):
+        s.solve(f, g, tol=args.tol, max_cycles=100, out=u)
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - t0) * 1e3
+    for s in solvers:
+        s.close()
+    log(f"[bench] sequential fp64 over the same batch: {ms_seq:.1f} ms")
+    return {"value": dof / (ms * 1e-3), "unit": "DOF/s", "ms_per_step": ms, "problems": len(probs),
+            "active_dof": dof, "N_counts": {str(n): Ns.count(n) for n in sorted(set(Ns))},
+            "cycles_max": max(cycles), "cycles_mean": float(np.mean(cycles)),
+            "worst_final_rel_residual": worst, "autotuned_tile": tile, "setup_s": setup_s,
+            "fp64_sequential_ms": ms_seq, "speedup_vs_fp64_sequential": ms_seq / ms,
+            "dtype": "f32 cycles / f64 refinement"}
+
+
+def bs_info_dof(bs, mg):
+    import ctypes as C
+    from paper_2505_05105_amd import _lib
+    inf = _lib.Info()
+    _lib.check(_lib.lib().mgfem_query(bs.handle, C.byref(inf)), bs.handle)
+    return inf.n_active
+
+
+def bench_adjoint(args, mg, W, torch, dev):
+    """Adjoint workload: flower, N = 2048, misfit against u_t = cos(2 pi x) sin(pi y);
+    the transposed cycles run as many cycles as the forward solve took."""
+    N = 2048
+    prob = W.flower_mms(N)
+    s = mg.Solver(prob.psi, N)
+    f = torch.tensor(prob.f, device=dev)
+    g = torch.tensor(prob.g, device=dev)
+    ut = torch.tensor(W.adjoint_target(N), device=dev)
+    u, hist = s.solve(f, g, tol=args.tol, max_cycles=100)
+    k = len(hist) - 1
+    _, dJdu = s.misfit(u, ut)
+    for _ in range(args.warmup):
+        s.adjoint(dJdu, tol=-1.0, max_cycles=k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        df, dg, lam, ha = s.adjoint(dJdu, tol=-1.0, max_cycles=k)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    dof = s.info()["n_active"]
+    log(f"[bench] adjoint N={N}: {ms:.2f} ms ({k} transposed cycles)")
+    s.close()
+    return {"value": dof / (ms * 1e-3), "unit": "DOF/s", "ms_per_step": ms, "N": N, "active_dof": dof,
+            "cycles": k, "final_rel_residual": float(ha[-1] / ha[0]), "dtype": "f64"}
 
 
 def _cpu_name():
@@ -197,6 +287,11 @@ def main():
                         "speedup_vs_fp64": ms / msm}
         log(f"[bench] mixed: {msm:.3f} ms/solve, {len(hm) - 1} cycles, err vs fp64 {err:.2e}")
         smx.close()
+
+    if not args.no_extras:
+        s64.close()
+        out["batched"] = bench_batched(args, mg, W, torch, dev)
+        out["adjoint"] = bench_adjoint(args, mg, W, torch, dev)
 
     if args.copy_probe:
         # a plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for it calibrates the counters

@@ -244,6 +244,10 @@ int mgfem_solve_batched(mgfem_handle h, const double* const* f_dev, const double
                         double rel_tol, int32_t max_cycles, double* const* u_dev,
                         double* res_hist_host, int32_t* n_cycles);
 
+/* Footprint width (nodes per row of a workgroup's 1024-thread footprint on a
+ * colour sub-lattice) picked by the batched autotuner, or -1. */
+int mgfem_batched_tile(mgfem_handle h);
+
 #ifdef __cplusplus
 }
 #endif

@@ -214,6 +214,17 @@ class BatchedSolver:
         hist = hist.reshape(cnt, max_cycles + 1)
         return outs, [hist[i, : ncyc[i] + 1] for i in range(cnt)]
 
+    @property
+    def tile(self):
+        """Footprint width chosen by the autotuner."""
+        return _lib.lib().mgfem_batched_tile(self.handle)
+
+    def last_ms(self):
+        """Device time of the last batched solve (one persistent launch)."""
+        inf = _lib.Info()
+        _lib.check(_lib.lib().mgfem_query(self.handle, C.byref(inf)), self.handle)
+        return inf.setup_ms
+
     def close(self):
         if getattr(self, "handle", None):
             _lib.lib().mgfem_destroy(self.handle)

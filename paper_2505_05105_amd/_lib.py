@@ -25,7 +25,7 @@ EXPORTED = (
     "mgfem_default_params", "mgfem_setup", "mgfem_solve", "mgfem_adjoint", "mgfem_misfit",
     "mgfem_query", "mgfem_export", "mgfem_level_n", "mgfem_smooth", "mgfem_destroy",
     "mgfem_status_string", "mgfem_last_error", "mgfem_setup_batched", "mgfem_solve_batched",
-    "mgfem_level_counts", "mgfem_profile", "mgfem_profile_read",
+    "mgfem_level_counts", "mgfem_profile", "mgfem_profile_read", "mgfem_batched_tile",
 )
 
 
@@ -81,6 +81,7 @@ def lib():
                                          C.POINTER(C.c_int64)]),
         "mgfem_profile": (C.c_int, [P, I32]),
         "mgfem_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP, DP]),
+        "mgfem_batched_tile": (C.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

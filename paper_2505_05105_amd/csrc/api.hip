@@ -44,6 +44,8 @@ int check_params(const mgfem_params& p, int N, std::string& why) {
 }  // namespace
 
 namespace mgfem {
+void set_setup_error(const std::string& msg) { g_setup_error = msg; }
+
 hipError_t ctx_alloc(mgfem_ctx* c, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 8;
@@ -256,6 +258,8 @@ int32_t mgfem_level_n(mgfem_handle h, int32_t level) {
 
 int mgfem_destroy(mgfem_handle h) {
   if (!h) return MGFEM_ERR_INVALID_ARG;
+  for (mgfem_ctx* m : h->members) free_ctx(m);
+  h->members.clear();
   free_ctx(h);
   return MGFEM_OK;
 }

@@ -1,22 +1,219 @@
-// Batched solves: placeholder entry points (implemented below in a later
-// revision of this file).
+// Batched solves: many independent problems (different level sets and N)
+// behind one handle, solved in one persistent launch (see k_batched).
+//
+// Setup builds one mixed-precision hierarchy per problem with the single-
+// problem setup, then a table of per-problem layout records.  The footprint
+// width of the workgroup's colour-phase loops is picked by a small autotuner:
+// each candidate runs two cycles of the whole batch on zero data, the
+// fastest wins, and the choice is kept per (device, batch shape) in the
+// process and, when MGFEM_TUNE_CACHE names a file, in that file.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+
 #include "mgfem_internal.h"
+
+using namespace mgfem;
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+
+std::string tune_key(const std::vector<int>& Ns, const mgfem_params& p) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  long long sum = 0;
+  for (int n : Ns) sum += (long long)(n + 1) * (n + 1);
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s|count=%zu|nodes=%lld|eta=%d|nu=%d,%d", arch.c_str(), Ns.size(), sum, p.eta,
+                p.nu1, p.nu2);
+  return buf;
+}
+
+int cache_lookup(const std::string& key) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it != g_tune.end()) return it->second;
+  const char* path = std::getenv("MGFEM_TUNE_CACHE");
+  if (!path) return 0;
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return 0;
+  char line[512];
+  int found = 0;
+  while (std::fgets(line, sizeof line, fh)) {
+    char k[400];
+    int tx;
+    if (std::sscanf(line, "%399s %d", k, &tx) == 2 && key == k) found = tx;
+  }
+  std::fclose(fh);
+  if (found) g_tune[key] = found;
+  return found;
+}
+
+void cache_store(const std::string& key, int tx) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = tx;
+  const char* path = std::getenv("MGFEM_TUNE_CACHE");
+  if (!path) return;
+  FILE* fh = std::fopen(path, "a");
+  if (!fh) return;
+  std::fprintf(fh, "%s %d\n", key.c_str(), tx);
+  std::fclose(fh);
+}
+
+void free_batch(mgfem_ctx* b) {
+  for (mgfem_ctx* m : b->members) mgfem_destroy(m);
+  b->members.clear();
+}
+
+}  // namespace
 
 extern "C" {
 
-int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32_t* N,
-                        const mgfem_params* p, void* stream, mgfem_handle* out) {
-  (void)count; (void)psi_dev; (void)N; (void)p; (void)stream;
-  if (out) *out = nullptr;
-  return MGFEM_ERR_UNSUPPORTED;
+int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32_t* N, const mgfem_params* pin,
+                        void* stream, mgfem_handle* out) {
+  if (!out) return MGFEM_ERR_INVALID_ARG;
+  *out = nullptr;
+  if (count <= 0 || !psi_dev || !N) return MGFEM_ERR_INVALID_ARG;
+  mgfem_params p;
+  if (pin) p = *pin;
+  else mgfem_default_params(&p);
+  p.precision = MGFEM_PREC_MIXED;  // float32 cycles with float64 refinement
+  p.cycle = MGFEM_CYCLE_V;
+  mgfem_ctx* b = new mgfem_ctx();
+  b->p = p;
+  b->s = reinterpret_cast<hipStream_t>(stream);
+  auto bail = [&](int code, const std::string& msg) {
+    free_batch(b);
+    for (void* q : b->allocs) (void)hipFree(q);
+    delete b;
+    set_setup_error(msg);
+    return code;
+  };
+  for (int i = 0; i < count; ++i) {
+    mgfem_handle h = nullptr;
+    const int rc = mgfem_setup(psi_dev[i], N[i], &p, stream, &h);
+    if (rc != MGFEM_OK) {
+      const std::string why = mgfem_last_error(nullptr);
+      return bail(rc, "problem " + std::to_string(i) + ": " + why);
+    }
+    h->batched_member = true;
+    b->members.push_back(h);
+  }
+  std::vector<unsigned char> bytes;
+  int lds = 0;
+  build_batch_layout(b->members, bytes, lds);
+  for (mgfem_ctx* m : b->members) {
+    b->info.n_active += m->info.n_active;
+    b->info.N = std::max(b->info.N, m->info.N);
+    b->info.n_levels = std::max(b->info.n_levels, m->info.n_levels);
+  }
+  BatchDevice& d = b->batch;
+  d.lds = lds;
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return b->members[x]->lv[0].n_active > b->members[y]->lv[0].n_active;
+  });
+#define BTRY(x)                                                                     \
+  do {                                                                              \
+    hipError_t _e = (x);                                                            \
+    if (_e != hipSuccess) return bail(MGFEM_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+  BTRY(ctx_alloc(b, &d.probs, bytes.size()));
+  BTRY(hipMemcpyAsync(d.probs, bytes.data(), bytes.size(), hipMemcpyHostToDevice, b->s));
+  BTRY(ctx_alloc_t(b, &d.order, count));
+  BTRY(hipMemcpyAsync(d.order, order.data(), count * sizeof(int), hipMemcpyHostToDevice, b->s));
+  BTRY(ctx_alloc(b, reinterpret_cast<void**>(&d.f), count * sizeof(void*)));
+  BTRY(ctx_alloc(b, reinterpret_cast<void**>(&d.g), count * sizeof(void*)));
+  BTRY(ctx_alloc(b, reinterpret_cast<void**>(&d.u), count * sizeof(void*)));
+  BTRY(ctx_alloc_t(b, &d.ncyc, count));
+  BTRY(ctx_alloc_t(b, &d.queue, 1));
+  BTRY(hipStreamSynchronize(b->s));
+  // autotune the footprint width: two cycles of the whole batch on zero data
+  std::vector<int> Ns(N, N + count);
+  const std::string key = tune_key(Ns, p);
+  d.tx = cache_lookup(key);
+  if (d.tx == 0) {
+    std::vector<const double*> zf(count);
+    std::vector<double*> scratch(count);
+    for (int i = 0; i < count; ++i) {
+      zf[i] = b->members[i]->zero;
+      scratch[i] = b->members[i]->lam;
+    }
+    BTRY(hipMemcpyAsync(d.f, zf.data(), count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+    BTRY(hipMemcpyAsync(d.g, zf.data(), count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+    BTRY(hipMemcpyAsync(d.u, scratch.data(), count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+    const int cyc = 2;
+    BTRY(ctx_alloc_t(b, &d.hist, count * (cyc + 1)));
+    d.hist_cap = cyc + 1;
+    float best = 1e30f;
+    for (int tx : {32, 64, 128, 256}) {
+      (void)launch_batched(b, d, count, -1.0, cyc, tx);  // warm
+      const float ms = launch_batched(b, d, count, -1.0, cyc, tx);
+      BTRY(hipGetLastError());
+      if (ms < best) {
+        best = ms;
+        d.tx = tx;
+      }
+    }
+    cache_store(key, d.tx);
+  }
+#undef BTRY
+  *out = b;
+  return MGFEM_OK;
 }
 
-int mgfem_solve_batched(mgfem_handle h, const double* const* f_dev, const double* const* g_dev,
-                        double rel_tol, int32_t max_cycles, double* const* u_dev,
-                        double* res_hist_host, int32_t* n_cycles) {
-  (void)h; (void)f_dev; (void)g_dev; (void)rel_tol; (void)max_cycles; (void)u_dev;
-  (void)res_hist_host; (void)n_cycles;
-  return MGFEM_ERR_UNSUPPORTED;
+int mgfem_solve_batched(mgfem_handle b, const double* const* f_dev, const double* const* g_dev, double rel_tol,
+                        int32_t max_cycles, double* const* u_dev, double* res_hist_host, int32_t* n_cycles) {
+  if (!b || b->members.empty()) return MGFEM_ERR_INVALID_ARG;
+  const int count = (int)b->members.size();
+  if (!f_dev || !g_dev || !u_dev || max_cycles < 0) {
+    b->last_error = "f, g and u arrays of device pointers are required";
+    return MGFEM_ERR_INVALID_ARG;
+  }
+  BatchDevice& d = b->batch;
+  mgfem_ctx* c = b;
+  if (d.hist_cap < max_cycles + 1) {
+    MGFEM_HIP_TRY(ctx_alloc_t(b, &d.hist, (size_t)count * (max_cycles + 1)));
+    d.hist_cap = max_cycles + 1;
+  }
+  MGFEM_HIP_TRY(hipMemcpyAsync(d.f, f_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+  MGFEM_HIP_TRY(hipMemcpyAsync(d.g, g_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+  MGFEM_HIP_TRY(hipMemcpyAsync(d.u, u_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+  const float ms = launch_batched(b, d, count, rel_tol, max_cycles, d.tx);
+  MGFEM_HIP_TRY(hipGetLastError());
+  b->info.setup_ms = ms;  // device time of the last batched solve
+  std::vector<double> hist((size_t)count * (max_cycles + 1));
+  std::vector<int> nc(count);
+  MGFEM_HIP_TRY(hipMemcpyAsync(hist.data(), d.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, b->s));
+  MGFEM_HIP_TRY(hipMemcpyAsync(nc.data(), d.ncyc, count * sizeof(int), hipMemcpyDeviceToHost, b->s));
+  MGFEM_HIP_TRY(hipStreamSynchronize(b->s));
+  bool all = true;
+  for (int i = 0; i < count; ++i) {
+    const double* h = hist.data() + (size_t)i * (max_cycles + 1);
+    if (n_cycles) n_cycles[i] = nc[i];
+    if (res_hist_host)
+      std::memcpy(res_hist_host + (size_t)i * (max_cycles + 1), h, (max_cycles + 1) * sizeof(double));
+    const bool conv = rel_tol > 0.0 && h[nc[i]] <= rel_tol * h[0];
+    if (!conv && rel_tol > 0.0) all = false;
+  }
+  if (!all) {
+    b->last_error = "some problems did not reach the tolerance";
+    return MGFEM_ERR_NOT_CONVERGED;
+  }
+  return MGFEM_OK;
 }
+
+int mgfem_batched_tile(mgfem_handle b) { return b ? b->batch.tx : -1; }
 
 }  // extern "C"

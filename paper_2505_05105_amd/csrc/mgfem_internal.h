@@ -132,6 +132,20 @@ struct Stats {
   int coarse_n;
 };
 
+struct BatchDevice {
+  void* probs = nullptr;  // per-problem layout records (built in smoother.hip)
+  int* order = nullptr;   // problems by decreasing size (work-queue order)
+  const double** f = nullptr;
+  const double** g = nullptr;
+  double** u = nullptr;
+  double* hist = nullptr;
+  int hist_cap = 0;
+  int* ncyc = nullptr;
+  unsigned int* queue = nullptr;
+  int lds = 0;
+  int tx = 0;  // autotuned footprint width (0: not tuned yet)
+};
+
 }  // namespace mgfem
 
 struct mgfem_ctx {
@@ -169,11 +183,15 @@ struct mgfem_ctx {
   mgfem::Profiler prof;
   std::string last_error;
   bool batched_member = false;
+  std::vector<mgfem_ctx*> members;  // batched handle: one context per problem
+  mgfem::BatchDevice batch;
 };
 
 namespace mgfem {
 
 constexpr int kRedBlocks = 1024;
+
+void set_setup_error(const std::string& msg);  // text returned by mgfem_last_error(NULL)
 
 // memory helpers (record the allocation on the context)
 hipError_t ctx_alloc(mgfem_ctx* c, void** p, size_t bytes);
@@ -223,6 +241,9 @@ inline int sweep_shape(const mgfem_ctx* c, int l) {
   return N >= 1024 ? kShapeLarge : kShapeSmall;
 }
 void set_kernel_attributes();
+// batched solves (layout and launch in smoother.hip)
+void build_batch_layout(std::vector<mgfem_ctx*>& members, std::vector<unsigned char>& probs_bytes, int& lds);
+float launch_batched(mgfem_ctx* b, BatchDevice& d, int count, double tol, int max_cycles, int tx);
 // profiling: bracket a launch (returns the event pair index or -1) and collect
 int prof_begin(mgfem_ctx* c, int kernel_class, double bytes);
 void prof_end(mgfem_ctx* c, int slot);

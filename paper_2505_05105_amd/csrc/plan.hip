@@ -176,7 +176,7 @@ int build_plans(mgfem_ctx* c) {
   MGFEM_HIP_TRY(hipGetDevice(&dev));
   int lds_max = 65536;
   MGFEM_HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-  const size_t cap = (size_t)lds_max - 1024;
+  const size_t cap = (size_t)lds_max - 4096;  // room for the kernels' static LDS
   // --- cut positions, snapshots and cut groups, every level with smoothing
   const int D = 4 * c->p.eta;
   for (int l = 0; l + 1 < nl; ++l) {

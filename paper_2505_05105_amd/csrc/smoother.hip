@@ -27,6 +27,7 @@
 //  k_coarse     the V-cycle of all remaining coarse levels in one workgroup.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "mgfem_internal.h"
 
@@ -705,10 +706,10 @@ __device__ void wg_cycle(const CoarseArgs<T>& a, const int* sdesc, unsigned char
   }
 }
 
+// stage every coarse level into LDS, run gamma* cycles, write the first coarse
+// level's iterate back to global memory (ends with a barrier)
 template <class T>
-__global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char base[];
-  __shared__ int sdesc[kDesc * kMaxWgLevels];
+__device__ void coarse_body(const CoarseArgs<T>& a, unsigned char* base, int* sdesc) {
   for (int q = threadIdx.x; q < kDesc * a.nlev; q += blockDim.x) sdesc[q] = a.desc[q];
   for (int l = 0; l < a.nlev; ++l) {
     const int* d = a.desc + kDesc * l;
@@ -749,6 +750,14 @@ __global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
     const int gi = L.ox + q % L.W, gj = L.oy + q / L.W;
     a.x_top[gi + (int64_t)gj * a.s_top] = L.x[q];
   }
+  __syncthreads();
+}
+
+template <class T>
+__global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char base[];
+  __shared__ int sdesc[kDesc * kMaxWgLevels];
+  coarse_body<T>(a, base, sdesc);
 }
 
 inline unsigned nblk(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); }
@@ -1073,6 +1082,412 @@ void gather_snap(mgfem_ctx* c, int l, bool fp32) {
   else
     hipLaunchKernelGGL(k_snap_gather<double>, dim3(nblk(cnt, 256)), dim3(256), 0, c->s, L.cut_list, cnt,
                        (const double*)L.X[L.cur], L.snap);
+}
+
+}  // namespace mgfem
+
+// ===========================================================================
+// Batched solves in one persistent launch.
+//
+// Every workgroup (1024 threads) takes whole problems from a work queue (an
+// atomic counter over the problems ordered by decreasing size) and solves
+// each one alone: no workgroup ever waits for another, and each exits when
+// the queue is empty.  Per problem: F = M f + G g, then float64 defect
+// correction around float32 V(nu1, nu2) cycles.  On the grid levels above the
+// LDS-resident coarse part, a colour phase updates its nodes in place in
+// global memory (one workgroup, so a barrier separates the phases; nodes of
+// one colour never neighbour each other); the coarse levels run in LDS as in
+// the single-problem solver.  Threads cover each colour sub-lattice in
+// footprints of tx x (1024 / tx) nodes; tx is chosen by the autotuner.
+// ===========================================================================
+namespace mgfem {
+namespace {
+
+template <class F>
+__device__ inline void wg_for_sublattice(int i0, int i1, int j0, int j1, int cx, int cy, int tx, F&& f) {
+  // nodes (i, j) of the box with i = cx, j = cy (mod 2); cx = -1 / cy = -1: every node
+  const int fi = cx < 0 ? i0 : i0 + ((cx - i0) & 1), fj = cy < 0 ? j0 : j0 + ((cy - j0) & 1);
+  const int di = cx < 0 ? 1 : 2, dj = cy < 0 ? 1 : 2;
+  if (fi > i1 || fj > j1) return;
+  const int ni = (i1 - fi) / di + 1, nj = (j1 - fj) / dj + 1;
+  const int ty = 1024 / tx;
+  const int lx = threadIdx.x % tx, ly = threadIdx.x / tx;
+  for (int pj = 0; pj < nj; pj += ty) {
+    const int tj = pj + ly;
+    if (tj >= nj) continue;
+    for (int pi = 0; pi < ni; pi += tx) {
+      const int ti = pi + lx;
+      if (ti < ni) f(fi + di * ti, fj + dj * tj);
+    }
+  }
+}
+
+// row product of node k (i, j) against x in global memory; returns the full
+// product, with the diagonal and the off-diagonal part; rows on the grid edge
+// skip the neighbours outside the grid
+template <class T>
+__device__ inline T glob_row(const T* __restrict__ A, int64_t n, const T* x, int64_t k, int i, int j, int N, int s,
+                             bool stored, T& diag, T& off) {
+  if (stored) {
+    diag = A[4 * n + k];
+    if (i > 0 && j > 0 && i < N && j < N) {
+      off = A[k] * x[k - s - 1] + A[n + k] * x[k - s] + A[2 * n + k] * x[k - s + 1] + A[3 * n + k] * x[k - 1] +
+            A[5 * n + k] * x[k + 1] + A[6 * n + k] * x[k + s - 1] + A[7 * n + k] * x[k + s] +
+            A[8 * n + k] * x[k + s + 1];
+    } else {
+      off = T(0);
+      for (int q = 0; q < 9; ++q) {
+        if (q == 4) continue;
+        const int ii = i + q % 3 - 1, jj = j + q / 3 - 1;
+        if (ii < 0 || jj < 0 || ii > N || jj > N) continue;
+        off += A[q * n + k] * x[ii + (int64_t)jj * s];
+      }
+    }
+  } else {  // interior Q1 row: every neighbour exists
+    diag = T(8) / T(3);
+    off = -((x[k - s - 1] + x[k - s] + x[k - s + 1]) + (x[k - 1] + x[k + 1]) +
+            (x[k + s - 1] + x[k + s] + x[k + s + 1])) / T(3);
+  }
+  return diag * x[k] + off;
+}
+
+struct BLevel {
+  int N, s, i0, i1, j0, j1;
+  int64_t n;
+  const float* A;
+  const uint8_t* fl;
+  float* x;
+  float* r;
+  float* b;
+  const int* cut;
+  int cut_off[5];
+};
+
+constexpr int kMaxBLevels = 16;
+
+struct BProb {
+  int nlev;  // grid levels above the coarse workgroup part
+  int N0, s0, i0, i1, j0, j1;
+  int64_t n0;
+  const double* A64;
+  const uint8_t* fl0;
+  const double* M;
+  const double* G;
+  double* F;
+  double* r64;
+  BLevel lev[kMaxBLevels];
+  CoarseArgs<float> ca;
+};
+
+struct BatchArgs {
+  const BProb* probs;
+  const int* order;
+  int count;
+  const double* const* f;
+  const double* const* g;
+  double* const* u;
+  double* hist;  // count x (max_cycles + 1)
+  int* ncyc;
+  double tol;
+  int max_cycles, nu1, nu2, eta, tx;
+  unsigned int* queue;
+};
+
+// workgroup reduction of (max, sum); every thread gets the result
+__device__ inline void wg_reduce2(double& mx, double& sm, double* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = nanmax2(mx, __shfl_xor(mx, o));
+    sm += __shfl_xor(sm, o);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[2 * w] = mx;
+    red[2 * w + 1] = sm;
+  }
+  __syncthreads();
+  mx = 0.0;
+  sm = 0.0;
+  for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+    mx = nanmax2(mx, red[2 * q]);
+    sm += red[2 * q + 1];
+  }
+  __syncthreads();
+}
+
+__device__ void b_smooth(const BLevel& L, int eta, int tx) {
+  for (int c = 0; c < 4; ++c) {
+    wg_for_sublattice(L.i0, L.i1, L.j0, L.j1, c & 1, c >> 1, tx, [&](int i, int j) {
+      const int64_t k = i + (int64_t)j * L.s;
+      const uint8_t f = L.fl[k];
+      if (!(f & kFlagActive)) return;
+      float diag, off;
+      (void)glob_row<float>(L.A, L.n, L.x, k, i, j, L.N, L.s, (f & kFlagStored) != 0, diag, off);
+      L.x[k] = (L.b[k] - off) / diag;
+    });
+    __syncthreads();
+  }
+  for (int e = 0; e < eta; ++e)
+    for (int c = 0; c < 4; ++c) {
+      for (int t = L.cut_off[c] + threadIdx.x; t < L.cut_off[c + 1]; t += blockDim.x) {
+        const int64_t k = L.cut[t];
+        float diag, off;
+        (void)glob_row<float>(L.A, L.n, L.x, k, (int)(k % L.s), (int)(k / L.s), L.N, L.s, true, diag, off);
+        L.x[k] = (L.b[k] - off) / diag;
+      }
+      __syncthreads();
+    }
+}
+
+__device__ void b_restrict(const BLevel& L, const BLevel& C, int tx) {
+  wg_for_sublattice(L.i0, L.i1, L.j0, L.j1, -1, -1, tx, [&](int i, int j) {
+    const int64_t k = i + (int64_t)j * L.s;
+    const uint8_t f = L.fl[k];
+    if (!(f & kFlagActive)) return;
+    float diag, off;
+    L.r[k] = L.b[k] - glob_row<float>(L.A, L.n, L.x, k, i, j, L.N, L.s, (f & kFlagStored) != 0, diag, off);
+  });
+  __syncthreads();
+  wg_for_sublattice(C.i0, C.i1, C.j0, C.j1, -1, -1, tx, [&](int I, int J) {
+    const int64_t kc = I + (int64_t)J * C.s;
+    if (!(C.fl[kc] & kFlagActive)) return;
+    const int fi = 2 * I, fj = 2 * J;
+    float v = 0.f;
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int jj = fj + dj;
+      if (jj < 0 || jj > L.N) continue;
+      const float* rr = L.r + (int64_t)jj * L.s;
+      float row = rr[fi], side = 0.f;
+      if (fi > 0) side += rr[fi - 1];
+      if (fi < L.N) side += rr[fi + 1];
+      v += (dj == 0 ? 1.f : 0.5f) * (row + 0.5f * side);
+    }
+    C.b[kc] = v;
+    C.x[kc] = 0.f;
+  });
+  __syncthreads();
+}
+
+__device__ void b_prolong(const BLevel& L, const BLevel& C, int tx) {
+  wg_for_sublattice(L.i0, L.i1, L.j0, L.j1, -1, -1, tx, [&](int i, int j) {
+    const int64_t k = i + (int64_t)j * L.s;
+    if (!(L.fl[k] & kFlagActive)) return;
+    const int I0 = i >> 1, I1 = (i + 1) >> 1, J0 = j >> 1, J1 = (j + 1) >> 1;
+    const float* xc = C.x;
+    const int64_t r0 = (int64_t)J0 * C.s, r1 = (int64_t)J1 * C.s;
+    L.x[k] += 0.25f * ((xc[I0 + r0] + xc[I1 + r0]) + (xc[I0 + r1] + xc[I1 + r1]));
+  });
+  __syncthreads();
+}
+
+// float64 residual r64 = F - A u over level 0 with (max |r|, sum r^2)
+__device__ void b_residual64(const BProb& P, const double* u, double& mx, double& sm, int tx, double* red) {
+  mx = 0.0;
+  sm = 0.0;
+  wg_for_sublattice(P.i0, P.i1, P.j0, P.j1, -1, -1, tx, [&](int i, int j) {
+    const int64_t k = i + (int64_t)j * P.s0;
+    const uint8_t f = P.fl0[k];
+    if (!(f & kFlagActive)) return;
+    double diag, off;
+    const double r =
+        P.F[k] - glob_row<double>(P.A64, P.n0, u, k, i, j, P.N0, P.s0, (f & kFlagStored) != 0, diag, off);
+    P.r64[k] = r;
+    mx = nanmax2(mx, fabs(r));
+    sm += r * r;
+  });
+  wg_reduce2(mx, sm, red);
+}
+
+__device__ void solve_one(const BatchArgs& a, int p, unsigned char* base, int* sdesc, double* red) {
+  const BProb& P = a.probs[p];
+  double* u = a.u[p];
+  const double* f = a.f[p];
+  const double* g = a.g[p];
+  const int tx = a.tx;
+  double* hist = a.hist + (int64_t)p * (a.max_cycles + 1);
+  // u = 0 everywhere; F = M f + G g on the active nodes
+  for (int64_t k = threadIdx.x; k < P.n0; k += blockDim.x) u[k] = 0.0;
+  wg_for_sublattice(P.i0, P.i1, P.j0, P.j1, -1, -1, tx, [&](int i, int j) {
+    const int64_t k = i + (int64_t)j * P.s0;
+    double acc = 0.0;
+    if (P.fl0[k] & kFlagActive)
+      for (int q = 0; q < 9; ++q) {
+        const int ii = i + q % 3 - 1, jj = j + q / 3 - 1;
+        if (ii < 0 || jj < 0 || ii > P.N0 || jj > P.N0) continue;
+        const int64_t kk = ii + (int64_t)jj * P.s0;
+        const double m = P.M[q * P.n0 + k], gg = P.G[q * P.n0 + k];
+        if (m != 0.0) acc += m * f[kk];
+        if (gg != 0.0) acc += gg * g[kk];
+      }
+    P.F[k] = acc;
+  });
+  __syncthreads();
+  double mx, sm;
+  b_residual64(P, u, mx, sm, tx, red);
+  hist[0] = mx;
+  const double fnorm = mx;
+  int m = 0;
+  double prev = mx;
+  int grow = 0;
+  // rel_tol <= 0: exactly max_cycles cycles
+  while (m < a.max_cycles && !(a.tol > 0.0 && mx <= a.tol * fnorm) && mx == mx) {
+    // inner float32 cycle on A e = r from e = 0
+    const BLevel& L0 = P.lev[0];
+    wg_for_sublattice(P.i0, P.i1, P.j0, P.j1, -1, -1, tx, [&](int i, int j) {
+      const int64_t k = i + (int64_t)j * P.s0;
+      L0.b[k] = (float)P.r64[k];
+      L0.x[k] = 0.f;
+    });
+    __syncthreads();
+    for (int l = 0; l < P.nlev; ++l) {
+      for (int s = 0; s < a.nu1; ++s) b_smooth(P.lev[l], a.eta, tx);
+      b_restrict(P.lev[l], P.lev[l + 1], tx);
+    }
+    coarse_body<float>(P.ca, base, sdesc);
+    for (int l = P.nlev - 1; l >= 0; --l) {
+      b_prolong(P.lev[l], P.lev[l + 1], tx);
+      for (int s = 0; s < a.nu2; ++s) b_smooth(P.lev[l], a.eta, tx);
+    }
+    // float64 update and residual
+    wg_for_sublattice(P.i0, P.i1, P.j0, P.j1, -1, -1, tx, [&](int i, int j) {
+      const int64_t k = i + (int64_t)j * P.s0;
+      if (P.fl0[k] & kFlagActive) u[k] += (double)L0.x[k];
+    });
+    __syncthreads();
+    b_residual64(P, u, mx, sm, tx, red);
+    ++m;
+    hist[m] = mx;
+    grow = mx > prev ? grow + 1 : 0;
+    if (grow >= 3) break;
+    prev = mx;
+  }
+  if (threadIdx.x == 0) a.ncyc[p] = m;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_batched(BatchArgs a) {
+  extern __shared__ __align__(16) unsigned char base[];
+  __shared__ int sdesc[kDesc * kMaxWgLevels];
+  __shared__ double red[32];
+  __shared__ int sidx;
+  while (true) {
+    if (threadIdx.x == 0) sidx = (int)atomicAdd(a.queue, 1u);
+    __syncthreads();
+    const int q = sidx;
+    __syncthreads();
+    if (q >= a.count) break;  // queue empty: every workgroup ends here
+    solve_one(a, a.order[q], base, sdesc, red);
+  }
+}
+
+}  // namespace
+
+}  // namespace mgfem
+
+namespace mgfem {
+
+size_t bprob_size() { return sizeof(BProb); }
+
+// one BProb per member context (set up in mixed precision)
+void build_batch_layout(std::vector<mgfem_ctx*>& members, std::vector<unsigned char>& probs_bytes, int& lds) {
+  probs_bytes.assign(members.size() * sizeof(BProb), 0);
+  lds = 0;
+  for (size_t i = 0; i < members.size(); ++i) {
+    mgfem_ctx* c = members[i];
+    BProb P{};
+    const int lc = c->cplan.lc;
+    P.nlev = lc;
+    Level& L0 = c->lv[0];
+    P.N0 = L0.N;
+    P.s0 = L0.stride;
+    P.n0 = L0.n;
+    P.i0 = L0.bbox[0];
+    P.i1 = L0.bbox[1];
+    P.j0 = L0.bbox[2];
+    P.j1 = L0.bbox[3];
+    P.A64 = L0.A;
+    P.fl0 = L0.flags;
+    P.M = c->M;
+    P.G = c->G;
+    P.F = c->F;
+    P.r64 = c->F64tmp;
+    for (int l = 0; l <= lc && l < kMaxBLevels; ++l) {
+      Level& L = c->lv[l];
+      BLevel& B = P.lev[l];
+      B.N = L.N;
+      B.s = L.stride;
+      B.n = L.n;
+      B.i0 = L.bbox[0];
+      B.i1 = L.bbox[1];
+      B.j0 = L.bbox[2];
+      B.j1 = L.bbox[3];
+      B.A = L.A32;
+      B.fl = L.flags;
+      B.x = L.X32[0];
+      B.r = L.X32[1];
+      B.b = L.b32;
+      B.cut = L.cut_list;
+      for (int q = 0; q < 5; ++q) B.cut_off[q] = L.cut_off[q];
+    }
+    CoarsePlan& CP = c->cplan;
+    CoarseArgs<float>& A = P.ca;
+    A.desc = CP.desc + kDesc * CP.ndesc;
+    A.coef = CP.coef32;
+    A.slot = CP.slot;
+    A.cutl = CP.cutl;
+    A.actl = CP.actl;
+    A.inv = CP.inv;
+    A.cidx = nullptr;
+    A.cn = c->coarse_n;
+    A.nlev = CP.ndesc;
+    A.b_top = c->lv[lc].b32;
+    A.x_top = c->lv[lc].X32[0];
+    A.s_top = c->lv[lc].stride;
+    A.nu1 = c->p.nu1;
+    A.nu2 = c->p.nu2;
+    A.eta = c->p.eta;
+    A.reverse = 0;
+    A.gstar = 1;
+    lds = std::max(lds, CP.lds32);
+    std::memcpy(probs_bytes.data() + i * sizeof(BProb), &P, sizeof(BProb));
+  }
+}
+
+float launch_batched(mgfem_ctx* b, BatchDevice& d, int count, double tol, int max_cycles, int tx) {
+  BatchArgs a;
+  a.probs = reinterpret_cast<const BProb*>(d.probs);
+  a.order = d.order;
+  a.count = count;
+  a.f = d.f;
+  a.g = d.g;
+  a.u = d.u;
+  a.hist = d.hist;
+  a.ncyc = d.ncyc;
+  a.tol = tol;
+  a.max_cycles = max_cycles;
+  a.nu1 = b->p.nu1;
+  a.nu2 = b->p.nu2;
+  a.eta = b->p.eta;
+  a.tx = tx;
+  a.queue = d.queue;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_batched), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            d.lds);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  (void)hipMemsetAsync(d.queue, 0, sizeof(unsigned int), b->s);
+  (void)hipEventRecord(e0, b->s);
+  hipLaunchKernelGGL(k_batched, dim3(std::min(count, cus)), dim3(1024), d.lds, b->s, a);
+  (void)hipEventRecord(e1, b->s);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
 }
 
 }  // namespace mgfem

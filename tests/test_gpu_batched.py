@@ -1,0 +1,57 @@
+"""GPU parity of the batched form (one persistent launch for many problems):
+every problem against the oracle, and against the single-problem solver."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assembly as oasm
+from oracle import multigrid as omg
+
+from helpers import rel_max
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_05105_amd as mg
+    return mg
+
+
+def test_batched_matches_oracle_per_problem():
+    mg = _gpu()
+    probs = W.batched_draws(count=8, seed=0, sizes=(32, 64, 128))
+    bs = mg.BatchedSolver([p.psi for p in probs], [p.N for p in probs])
+    assert bs.tile in (32, 64, 128, 256)
+    for tol in (1e-10, 1e-12):
+        us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=tol, max_cycles=80)
+        assert bs.last_status == 0
+        for p, u, h in zip(probs, us, hists):
+            d = oasm.assemble(p.psi, p.N)
+            F = d.rhs(p.f, p.g)
+            ref = omg.solve(omg.build_hierarchy(d), F, tol=1e-14, max_cycles=100)
+            assert h[-1] <= tol * h[0]
+            assert h[0] == pytest.approx(np.abs(F).max(), rel=1e-12)
+            ug = u.cpu().numpy()
+            assert np.all(ug[~d.active] == 0)
+            # single-problem FP64 solve at the same tolerance sets the error scale
+            s = mg.Solver(p.psi, p.N)
+            u64, _ = s.solve(p.f, p.g, tol=tol, max_cycles=80)
+            err64 = rel_max(u64.cpu().numpy(), ref.u)
+            assert rel_max(ug, ref.u) < 10 * err64 + 1e-13
+
+
+def test_batched_fixed_cycles_equal_single_mixed():
+    """Same cycles in float32 as the single-problem mixed solver (the batched
+    form updates in place over global memory, the single form in LDS tiles):
+    equal up to float32 rounding."""
+    mg = _gpu()
+    probs = W.batched_draws(count=3, seed=4, sizes=(64, 128))
+    bs = mg.BatchedSolver([p.psi for p in probs], [p.N for p in probs])
+    us, _ = bs.solve([p.f for p in probs], [p.g for p in probs], tol=-1.0, max_cycles=3)
+    for p, u in zip(probs, us):
+        s = mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
+        um, _ = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
+        assert rel_max(u.cpu().numpy(), um.cpu().numpy()) < 1e-4
