@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <cstdio>
+#include <cstdlib>
 #include <chrono>
 #include <new>
 
@@ -57,19 +59,68 @@ hipError_t ctx_alloc(mgfem_ctx* c, void** p, size_t bytes) {
 }  // namespace mgfem
 
 namespace mgfem {
-int prof_begin(mgfem_ctx* c, int kernel_class, double bytes) {
+// capture segments: close the running capture into a graph segment
+static void cap_fail(mgfem_ctx* c, hipError_t e, const char* what) {
+  GraphEntry& g = *c->capturing;
+  if (e != hipSuccess && g.err == hipSuccess) {
+    g.err = e;
+    c->last_error = std::string("graph capture: ") + what + ": " + hipGetErrorString(e);
+  }
+}
+static void seg_close(mgfem_ctx* c, int slot) {
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+  cap_fail(c, e, "hipStreamEndCapture");
+  if (e == hipSuccess && graph) {
+    size_t nodes = 0;
+    e = hipGraphGetNodes(graph, nullptr, &nodes);
+    cap_fail(c, e, "hipGraphGetNodes");
+    if (e == hipSuccess && nodes > 0) {
+      GraphSeg sg;
+      sg.slot = slot;
+      e = hipGraphInstantiate(&sg.exec, graph, nullptr, nullptr, 0);
+      cap_fail(c, e, "hipGraphInstantiate");
+      if (e == hipSuccess) c->capturing->segs.push_back(sg);
+    }
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+}
+static void seg_open(mgfem_ctx* c) {
+  cap_fail(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+}
+
+void prof_launch(mgfem_ctx* c, int kernel_class, double bytes, std::function<void(hipStream_t)> launch) {
   Profiler& P = c->prof;
+  if (c->capturing) {
+    GraphEntry& g = *c->capturing;
+    const size_t i = g.slots.size();
+    if (2 * (i + 1) > P.cap_ev.size()) {
+      cap_fail(c, hipErrorInvalidValue, "too many timed launches in one iteration");
+      return;
+    }
+    g.slots.push_back(ProfSlot{P.cap_ev[2 * i], P.cap_ev[2 * i + 1], kernel_class, bytes});
+    seg_close(c, -1);
+    GraphSeg sg;
+    sg.launch = std::move(launch);
+    sg.slot = (int)i;
+    g.segs.push_back(std::move(sg));
+    seg_open(c);
+    return;
+  }
   const int slot = (int)P.pending.size();
   while ((int)P.ev.size() < 2 * (slot + 1)) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return -1;
+    if (hipEventCreate(&e) != hipSuccess) {
+      launch(c->s);
+      return;
+    }
     P.ev.push_back(e);
   }
-  if (hipEventRecord(P.ev[2 * slot], c->s) != hipSuccess) return -1;
+  (void)hipEventRecord(P.ev[2 * slot], c->s);
+  launch(c->s);
+  (void)hipEventRecord(P.ev[2 * slot + 1], c->s);
   P.pending.push_back({kernel_class, bytes});
-  return slot;
 }
-void prof_end(mgfem_ctx* c, int slot) { (void)hipEventRecord(c->prof.ev[2 * slot + 1], c->s); }
 void prof_collect(mgfem_ctx* c) {
   Profiler& P = c->prof;
   if (P.pending.empty()) return;
@@ -84,6 +135,30 @@ void prof_collect(mgfem_ctx* c) {
   }
   P.pending.clear();
 }
+// timings of the launches inside one finished graph replay
+static int prof_collect_graph(mgfem_ctx* c, const GraphEntry& g) {
+  if (g.slots.empty()) return MGFEM_OK;
+  Profiler& P = c->prof;
+  MGFEM_HIP_TRY(hipEventSynchronize(g.slots.back().end));
+  for (const ProfSlot& sl : g.slots) {
+    float ms = 0.f;
+    MGFEM_HIP_TRY(hipEventElapsedTime(&ms, sl.beg, sl.end));
+    P.launches[sl.kernel_class] += 1;
+    P.ms[sl.kernel_class] += ms;
+    P.bytes[sl.kernel_class] += sl.bytes;
+  }
+  return MGFEM_OK;
+}
+static void destroy_graph(GraphEntry& g) {
+  for (GraphSeg& sg : g.segs)
+    if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+  g.segs.clear();
+  g.slots.clear();  // the events belong to the profiler
+}
+void drop_graphs(mgfem_ctx* c) {
+  for (auto& kv : c->graphs) destroy_graph(kv.second);
+  c->graphs.clear();
+}
 }  // namespace mgfem
 
 static void free_ctx(mgfem_ctx* c) {
@@ -91,6 +166,9 @@ static void free_ctx(mgfem_ctx* c) {
   if (c->s) (void)hipStreamSynchronize(c->s);
   else (void)hipDeviceSynchronize();
   for (hipEvent_t e : c->prof.ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->prof.cap_ev) (void)hipEventDestroy(e);
+  mgfem::drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* q : c->allocs) (void)hipFree(q);
   if (c->red_host) (void)hipHostFree(c->red_host);
   delete c;
@@ -193,6 +271,7 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
   SETUP_TRY(ctx_alloc_t(c, &c->lam, n0));
   SETUP_TRY(ctx_alloc_t(c, &c->red_partial, 2 * kRedBlocks));
   SETUP_TRY(ctx_alloc_t(c, &c->red_out, 2));
+  SETUP_TRY(ctx_alloc_t(c, &c->red_seq_dev, 1));
   SETUP_TRY(ctx_alloc_t(c, &c->sweep_counter, 1));
   {
     // one partial pair per level-0 sweep tile (64 x 32 tiles, or 32 x 16 below N = 1024)
@@ -201,6 +280,10 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
   }
   SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 4 * sizeof(double)));
   c->red_host[2] = 0.0;
+  {
+    const char* env = std::getenv("MGFEM_NO_GRAPHS");
+    c->use_graphs = !(env && env[0] && env[0] != '0');
+  }
   rc = setup_geometry(c, psi_dev);
   if (rc != MGFEM_OK) return bail(rc);
   rc = setup_hierarchy(c);
@@ -296,20 +379,171 @@ int read_norm(mgfem_ctx* c, double& mx, double& l2, double* raw_sum = nullptr) {
 
 // cycles on A x = b (x, b on level 0) until the relative tolerance is met;
 // x is the caller's buffer and receives the result
-int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cycles, bool reverse,
-            bool mixed, double* hist, int* ncyc) {
+// Enqueue one iteration of the solve loop: a cycle from the current iterate
+// and the reduction that gives the residual norm of the next one.
+//  float64 forward: the rest of the cycle (its first sweep ran in the previous
+//    iteration), then the first sweep of the next cycle with the fused norm of
+//    its incoming iterate (speculative: discarded when the loop stops);
+//  mixed: a float cycle from zero on the float residual of the previous
+//    step, then one fused pass u += e, r = F - A u (float64), its float copy,
+//    the next zero start iterate and the norm;
+//  adjoint: a transposed cycle, then the residual norm.
+struct IterKind {
+  bool mixed, reverse, first_done;
+};
+void enqueue_iteration(mgfem_ctx* c, const IterKind& k) {
   Level& L0 = c->lv[0];
-  double bnorm, dummy, r0, l2;
-  launch_residual_norm(c, b, c->zero, nullptr);
-  int rc = read_norm(c, bnorm, dummy);
-  if (rc) return rc;
-  launch_residual_norm(c, b, x, mixed ? c->F64tmp : nullptr);
-  rc = read_norm(c, r0, l2);
-  if (rc) return rc;
-  if (hist) hist[0] = r0;
-  L0.X[0] = x;
+  if (k.mixed) {
+    // the inner right-hand side b32 and the zero start iterate X32[cur] were
+    // written by the previous outer step
+    CycleOpts o;
+    o.fp32 = true;
+    o.reverse = k.reverse;
+    run_cycle(c, o);
+    const int ce = L0.cur;
+    launch_outer(c, L0.X[c->u_cur], L0.X32[ce], L0.X[1 - c->u_cur], L0.b32, L0.X32[1 - ce]);
+    c->u_cur = 1 - c->u_cur;
+    L0.cur = 1 - ce;
+  } else if (k.reverse) {
+    CycleOpts o;
+    o.reverse = true;
+    run_cycle(c, o);
+    launch_residual_norm(c, L0.b, L0.X[L0.cur], nullptr);
+  } else {
+    CycleOpts o;
+    o.first_sweep_done = k.first_done;
+    run_cycle(c, o);
+    first_sweep_with_norm(c);
+  }
+}
+
+// host-side state that an iteration reads and advances: the ping-pong parity
+// of every level and of the float64 level-0 iterate of the mixed solve
+std::vector<int> loop_state(const mgfem_ctx* c) {
+  std::vector<int> st;
+  for (const Level& L : c->lv) st.push_back(L.cur);
+  st.push_back(c->u_cur);
+  return st;
+}
+void set_loop_state(mgfem_ctx* c, const std::vector<int>& st) {
+  for (size_t l = 0; l < c->lv.size(); ++l) c->lv[l].cur = st[l];
+  c->u_cur = st[c->lv.size()];
+}
+
+std::vector<int> graph_key(mgfem_ctx* c, const IterKind& k) {
+  std::vector<int> key{k.mixed, k.reverse, k.first_done, c->prof.on ? 1 : 0};
+  for (int v : loop_state(c)) key.push_back(v);
+  return key;
+}
+
+// Run one iteration: replay its graph (captured on first use) or launch it
+// eagerly.  Returns the graph used, or null.
+int run_iteration(mgfem_ctx* c, const IterKind& k, const GraphEntry** used) {
+  *used = nullptr;
+  if (!c->use_graphs || c->graphs_failed) {
+    enqueue_iteration(c, k);
+    MGFEM_HIP_TRY(hipGetLastError());
+    return MGFEM_OK;
+  }
+  const std::vector<int> key = graph_key(c, k);
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (!c->cap_stream) MGFEM_HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    // the capture stream starts after the work already queued on the caller's
+    // stream only through the graph launch below, which is stream-ordered
+    if (c->prof.on && c->prof.cap_ev.empty()) {
+      // timed launches per iteration: three finest sweeps (W-cycle: the same)
+      for (int q = 0; q < 8; ++q) {
+        hipEvent_t e;
+        MGFEM_HIP_TRY(hipEventCreate(&e));
+        c->prof.cap_ev.push_back(e);
+      }
+    }
+    GraphEntry g;
+    hipStream_t user = c->s;
+    const double seq0 = c->red_seq;
+    const std::vector<int> st0 = loop_state(c);
+    c->s = c->cap_stream;
+    c->capturing = &g;
+    seg_open(c);
+    if (g.err == hipSuccess) {
+      enqueue_iteration(c, k);
+      seg_close(c, -1);
+    }
+    c->capturing = nullptr;
+    c->s = user;
+    g.nred = (int)(c->red_seq - seq0 + 0.5);
+    g.cur_after = loop_state(c);
+    c->red_seq = seq0;
+    set_loop_state(c, st0);
+    (void)hipGetLastError();
+    if (g.err != hipSuccess) {
+      // capture is not available here: run this context eagerly from now on
+      // (the reason stays readable through mgfem_last_error)
+      hipStreamCaptureStatus st;
+      if (hipStreamIsCapturing(c->cap_stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(c->cap_stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+      }
+      (void)hipGetLastError();
+      destroy_graph(g);
+      c->graphs_failed = true;
+      std::fprintf(stderr, "mgfem: %s; iterations run without graphs\n", c->last_error.c_str());
+      enqueue_iteration(c, k);
+      MGFEM_HIP_TRY(hipGetLastError());
+      return MGFEM_OK;
+    }
+    it = c->graphs.emplace(key, std::move(g)).first;
+  }
+  GraphEntry& g = it->second;
+  MGFEM_HIP_TRY(hipGetLastError());
+  for (const GraphSeg& sg : g.segs) {
+    if (sg.launch) {
+      MGFEM_HIP_TRY(hipEventRecord(g.slots[sg.slot].beg, c->s));
+      sg.launch(c->s);
+      MGFEM_HIP_TRY(hipEventRecord(g.slots[sg.slot].end, c->s));
+    } else {
+      MGFEM_HIP_TRY(hipGraphLaunch(sg.exec, c->s));
+    }
+  }
+  c->red_seq += g.nred;
+  set_loop_state(c, g.cur_after);
+  *used = &g;
+  return MGFEM_OK;
+}
+
+// x: caller's iterate (input when warm, output), b: level-0 right-hand side
+// (device buffer owned by the context).  The loop runs on the library's own
+// level-0 buffers so that captured graphs never see a caller pointer.
+int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cycles, bool reverse,
+            bool mixed, bool warm, double bnorm, double* hist, int* ncyc) {
+  Level& L0 = c->lv[0];
+  double dummy, r0, l2;
+  L0.X[0] = c->x0;
   L0.b = const_cast<double*>(b);
   L0.cur = 0;
+  c->u_cur = 0;
+  launch_box_copy(c, c->x0, warm ? x : nullptr);
+  int rc;
+  if (bnorm < 0.0) {
+    launch_residual_norm(c, b, c->zero, nullptr);
+    rc = read_norm(c, bnorm, dummy);
+    if (rc) return rc;
+  }
+  if (mixed) {
+    // r = F - A u, its float copy and the zero float start iterate
+    launch_outer(c, c->x0, nullptr, nullptr, L0.b32, L0.X32[0]);
+    rc = read_norm(c, r0, l2);
+    if (rc) return rc;
+  } else if (warm) {
+    launch_residual_norm(c, b, c->x0, nullptr);
+    rc = read_norm(c, r0, l2);
+    if (rc) return rc;
+  } else {
+    r0 = bnorm;  // u = 0
+  }
+  if (hist) hist[0] = r0;
   if (!mixed) gather_snap(c, 0, false);
   double prev = r0;
   int grow = 0, m = 0;
@@ -319,33 +553,17 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   const bool fused = !mixed && !reverse;  // norm of u_m from the first sweep of cycle m + 1
   bool first_done = false;
   while (status == MGFEM_OK && !conv && m < max_cycles) {
-    if (mixed) {
-      launch_cast_to_float(c, L0.b32, c->F64tmp, L0.n);
-      L0.cur = 0;
-      launch_zero_f(c, L0.X32[0], L0.n);
-      CycleOpts o;
-      o.fp32 = true;
-      o.reverse = reverse;
-      run_cycle(c, o);
-      launch_axpy_active(c, x, L0.X32[L0.cur]);
-      launch_residual_norm(c, b, x, c->F64tmp);
-    } else {
-      CycleOpts o;
-      o.reverse = reverse;
-      o.first_sweep_done = first_done;
-      run_cycle(c, o);
-      first_done = false;
-      if (fused && m + 1 < max_cycles) {
-        first_sweep_with_norm(c);  // leaves the iterate in place (ping-pong)
-        first_done = true;
-      } else {
-        launch_residual_norm(c, b, L0.X[L0.cur], nullptr);
-      }
-    }
-    MGFEM_HIP_TRY(hipGetLastError());
+    const GraphEntry* g = nullptr;
+    rc = run_iteration(c, IterKind{mixed, reverse, first_done}, &g);
+    if (rc) return rc;
+    first_done = fused;
     double rm;
     rc = read_norm(c, rm, l2);
     if (rc) return rc;
+    if (g && c->prof.on) {
+      rc = prof_collect_graph(c, *g);
+      if (rc) return rc;
+    }
     ++m;
     if (hist) hist[m] = rm;
     if (!std::isfinite(rm)) {
@@ -363,13 +581,13 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   // a speculative first sweep that is not followed by its cycle is discarded:
   // the iterate is still in the buffer it read from
   if (first_done) L0.cur = 1 - L0.cur;
-  if (!mixed && L0.cur == 1) launch_copy(c, x, L0.X[1], L0.n);
+  launch_export(c, x, mixed ? L0.X[c->u_cur] : L0.X[L0.cur]);
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   prof_collect(c);
-  L0.X[0] = nullptr;
   L0.b = nullptr;
   L0.cur = 0;
+  c->u_cur = 0;
   if (ncyc) *ncyc = m;
   if (status != MGFEM_OK) {
     c->last_error = "residual not finite or growing";
@@ -393,13 +611,16 @@ int mgfem_solve(mgfem_handle c, const double* f_dev, const double* g_dev, double
   if (c->batched_member) return fail(c, MGFEM_ERR_INVALID_ARG, "batched handle: use mgfem_solve_batched");
   if (!f_dev || !g_dev || !u_dev || max_cycles < 0)
     return fail(c, MGFEM_ERR_INVALID_ARG, "f, g and u must be device pointers; max_cycles >= 0");
+  const bool warm = (flags & MGFEM_SOLVE_WARM_START) != 0;
+  if (warm) launch_mask_inactive(c, u_dev);
   launch_rhs(c, f_dev, g_dev, c->F);
-  if (flags & MGFEM_SOLVE_WARM_START) launch_mask_inactive(c, u_dev);
-  else launch_zero(c, u_dev, c->lv[0].n);
   MGFEM_HIP_TRY(hipGetLastError());
+  double bnorm, l2;
+  int rc = read_norm(c, bnorm, l2);
+  if (rc) return rc;
   int nc = 0;
-  int rc = iterate(c, u_dev, c->F, rel_tol, max_cycles, false, c->p.precision == MGFEM_PREC_MIXED,
-                   res_hist_host, &nc);
+  rc = iterate(c, u_dev, c->F, rel_tol, max_cycles, false, c->p.precision == MGFEM_PREC_MIXED, warm, bnorm,
+               res_hist_host, &nc);
   if (n_cycles) *n_cycles = nc;
   return rc;
 }
@@ -410,12 +631,11 @@ int mgfem_adjoint(mgfem_handle c, const double* dJdu_dev, double rel_tol, int32_
   if (!c) return MGFEM_ERR_INVALID_ARG;
   if (!dJdu_dev || max_cycles < 0) return fail(c, MGFEM_ERR_INVALID_ARG, "dJdu must be a device pointer");
   double* lam = lam_dev ? lam_dev : c->lam;
-  launch_zero(c, lam, c->lv[0].n);
   // the adjoint right-hand side must vanish off the active nodes
   launch_sub_active(c, c->F, dJdu_dev, c->zero);
   MGFEM_HIP_TRY(hipGetLastError());
   int nc = 0;
-  int rc = iterate(c, lam, c->F, rel_tol, max_cycles, true, false, res_hist_host, &nc);
+  int rc = iterate(c, lam, c->F, rel_tol, max_cycles, true, false, false, -1.0, res_hist_host, &nc);
   if (n_cycles) *n_cycles = nc;
   if (rc != MGFEM_OK && rc != MGFEM_ERR_NOT_CONVERGED) return rc;
   if (dJdf_dev) launch_stencil_apply(c, c->M, lam, dJdf_dev, false);

@@ -310,11 +310,10 @@ int setup_hierarchy(mgfem_ctx* c) {
   // work vectors (zero-initialised: inactive entries are read but never written)
   for (int l = 0; l < nl; ++l) {
     Level& L = c->lv[l];
-    if (l > 0) {
-      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.X[0], L.n));
-      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.b, L.n));
-    }
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.X[0], L.n));
+    if (l > 0) MGFEM_HIP_TRY(ctx_alloc_t(c, &L.b, L.n));
     MGFEM_HIP_TRY(ctx_alloc_t(c, &L.X[1], L.n));
+    if (l == 0) c->x0 = L.X[0];
     if (mixed) {
       MGFEM_HIP_TRY(ctx_alloc_t(c, &L.A32, 9 * L.n));
       hipLaunchKernelGGL(k_to_float, dim3(nblk(9 * L.n, tb)), dim3(tb), 0, c->s, L.A, L.A32,

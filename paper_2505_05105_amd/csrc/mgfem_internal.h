@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -102,9 +104,36 @@ struct Profiler {
   bool on = false;
   std::vector<hipEvent_t> ev;  // pairs
   std::vector<std::pair<int, double>> pending;  // (kernel class, algorithmic bytes)
+  std::vector<hipEvent_t> cap_ev;  // pairs used by graph segments (created outside any capture)
   int64_t launches[4] = {0, 0, 0, 0};
   double ms[4] = {0, 0, 0, 0};
   double bytes[4] = {0, 0, 0, 0};
+};
+
+// One captured iteration of the solve loop (a cycle plus the reduction that
+// yields the next residual norm), replayed with one graph launch.  The host
+// bookkeeping (ping-pong parity of every level, reduction count) is a pure
+// function of the state at capture, so a graph is keyed by that state and
+// records the state it leaves behind.
+struct ProfSlot {
+  hipEvent_t beg, end;
+  int kernel_class;
+  double bytes;
+};
+// A timed launch is not captured: the entry keeps the launch itself and
+// replays it between graph segments, bracketed by an event pair on the
+// caller's stream (events around a graph launch cannot be timed).
+struct GraphSeg {
+  hipGraphExec_t exec = nullptr;
+  std::function<void(hipStream_t)> launch;  // timed eager launch (exec null)
+  int slot = -1;                            // index into GraphEntry::slots
+};
+struct GraphEntry {
+  std::vector<GraphSeg> segs;
+  std::vector<int> cur_after;  // loop state (ping-pong parities) after one replay
+  int nred = 0;                // reductions per replay
+  std::vector<ProfSlot> slots; // timed launches
+  hipError_t err = hipSuccess; // first capture error
 };
 
 // The coarsest levels run inside one workgroup, every array in LDS.
@@ -175,12 +204,21 @@ struct mgfem_ctx {
   double* red_out = nullptr;      // 2 doubles on device
   double* red_host = nullptr;     // pinned: max, sum of squares, sequence number
   double red_seq = 0.0;           // sequence number of the last reduction launched
+  double* red_seq_dev = nullptr;  // the same count kept on the device (bumped by each reduction kernel)
   double* sweep_part = nullptr;   // per-tile partials of the fused residual norm
   unsigned int* sweep_counter = nullptr;
   mgfem::Stats* stats = nullptr;  // device
   mgfem_info info{};
   std::vector<void*> allocs;
   mgfem::Profiler prof;
+  // graph replay of the solve loop
+  bool use_graphs = true;
+  bool graphs_failed = false;       // a capture failed: run this context eagerly
+  hipStream_t cap_stream = nullptr; // stream the iterations are captured on
+  mgfem::GraphEntry* capturing = nullptr;
+  std::map<std::vector<int>, mgfem::GraphEntry> graphs;
+  double* x0 = nullptr;             // level-0 iterate owned by the library (ping-pong partner of lv[0].X[1])
+  int u_cur = 0;                    // mixed precision: which level-0 float64 buffer holds u
   std::string last_error;
   bool batched_member = false;
   std::vector<mgfem_ctx*> members;  // batched handle: one context per problem
@@ -205,18 +243,23 @@ int setup_geometry(mgfem_ctx* c, const double* psi_in);
 int setup_hierarchy(mgfem_ctx* c);
 
 // solve stages (cycle.hip)
+// F = M f + G g, and its norm (max, sum of squares) as the next reduction
 void launch_rhs(mgfem_ctx* c, const double* f, const double* g, double* F);
+// mixed outer step: u_out = u + e, r = F - A u_out, r32 = float(r), z32 = 0 on
+// the active nodes, and the norm of r as the next reduction (F = lv[0].b)
+void launch_outer(mgfem_ctx* c, const double* u, const float* e, double* u_out, float* r32, float* z32);
 void launch_stencil_apply(mgfem_ctx* c, const double* planes, const double* x, double* y, bool transpose);
 void launch_mask_inactive(mgfem_ctx* c, double* u);
 void launch_residual_norm(mgfem_ctx* c, const double* F, const double* u, double* r_out);
 void launch_dot_reduce(mgfem_ctx* c, const double* a, const double* b);
 void launch_zero(mgfem_ctx* c, double* p, int64_t n);
 void launch_copy(mgfem_ctx* c, double* dst, const double* src, int64_t n);
-void launch_axpy_active(mgfem_ctx* c, double* u, const float* e);
-void launch_cast_to_float(mgfem_ctx* c, float* dst, const double* src, int64_t n);
 void launch_sub_active(mgfem_ctx* c, double* d, const double* a, const double* b);
-void launch_zero_f(mgfem_ctx* c, float* p, int64_t n);
 void launch_u8_to_f64(mgfem_ctx* c, const uint8_t* s, double* d, int64_t n);
+// level-0 bounding-box transfers: dst = src (or 0) on the box of active nodes;
+// export writes every node of dst (the box from src, zero outside)
+void launch_box_copy(mgfem_ctx* c, double* dst, const double* src);
+void launch_export(mgfem_ctx* c, double* dst, const double* src);
 
 struct CycleOpts {
   bool reverse = false;           // transposed cycle (adjoint)
@@ -244,10 +287,11 @@ void set_kernel_attributes();
 // batched solves (layout and launch in smoother.hip)
 void build_batch_layout(std::vector<mgfem_ctx*>& members, std::vector<unsigned char>& probs_bytes, int& lds);
 float launch_batched(mgfem_ctx* b, BatchDevice& d, int count, double tol, int max_cycles, int tx);
-// profiling: bracket a launch (returns the event pair index or -1) and collect
-int prof_begin(mgfem_ctx* c, int kernel_class, double bytes);
-void prof_end(mgfem_ctx* c, int slot);
+// profiling: a launch timed with HIP events (inside a capture it stays an
+// eager launch of the replay, see GraphSeg), and the collection of the timings
+void prof_launch(mgfem_ctx* c, int kernel_class, double bytes, std::function<void(hipStream_t)> launch);
 void prof_collect(mgfem_ctx* c);
+void drop_graphs(mgfem_ctx* c);
 
 }  // namespace mgfem
 

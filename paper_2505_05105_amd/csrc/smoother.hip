@@ -104,7 +104,7 @@ __device__ inline T gs_value(const T* __restrict__ A, int64_t n, int64_t k, bool
 //           the core is reduced into per-tile partials (max |r|, sum r^2).
 // final reduction of (max, sum) pairs in a fixed order
 __global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out, double* host_out,
-                               double seq) {
+                               double* seq) {
   __shared__ double smx[256], ssm[256];
   double mx = 0.0, sm = 0.0;
   for (int q = threadIdx.x; q < nb; q += blockDim.x) {
@@ -124,10 +124,12 @@ __global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* 
   if (threadIdx.x == 0) {
     out[0] = smx[0];
     out[1] = ssm[0];
+    const double q = seq[0] + 1.0;  // counted on the device (graph replays)
+    seq[0] = q;
     host_out[0] = smx[0];  // straight to pinned host memory; the sequence number goes last
     host_out[1] = ssm[0];
     __threadfence_system();
-    host_out[2] = seq;
+    host_out[2] = q;
     __threadfence_system();
   }
 }
@@ -824,20 +826,21 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   }
   a.per = (a.ntiles + 7) / 8;
   a.reverse = reverse ? 1 : 0;
-  int slot = -1;
   if (c->prof.on && std::is_same<T, double>::value && l == 0) {
     // algorithmic bytes: per active row x read and written, b read, its flag,
     // the 72 bytes of a stored row; a fused prolongation also reads x_c
     double bytes = 25.0 * L.n_active + 72.0 * L.n_stored;
     if (prolong_from) bytes += 8.0 * c->lv[l + 1].n_active;
-    slot = prof_begin(c, 0, bytes);
+    prof_launch(c, 0, bytes, [a](hipStream_t st) {
+      hipLaunchKernelGGL((k_sweep<T, TW, TH, BS>), dim3(8 * a.per), dim3(BS), 0, st, a);
+    });
+  } else {
+    hipLaunchKernelGGL((k_sweep<T, TW, TH, BS>), dim3(8 * a.per), dim3(BS), 0, c->s, a);
   }
-  hipLaunchKernelGGL((k_sweep<T, TW, TH, BS>), dim3(8 * a.per), dim3(BS), 0, c->s, a);
-  if (slot >= 0) prof_end(c, slot);
   if (norm) {
     c->red_seq += 1.0;
     hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, c->s, (const double*)c->sweep_part, a.ntiles,
-                       c->red_out, c->red_host, c->red_seq);
+                       c->red_out, c->red_host, c->red_seq_dev);
   }
   L.cur = 1 - L.cur;
 }

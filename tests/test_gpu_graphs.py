@@ -1,0 +1,95 @@
+"""Graph replay of the solve loop against eager launches of the same kernels.
+
+Each iteration of the solve loop is captured once and replayed; between
+replays the host reads the residual norm and the caller's own stream work runs
+(right-hand side, exports).  The replayed solves must equal the eager ones bit
+for bit (same kernels, same order), on every solve of a sequence.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_05105_amd as mg
+    return mg
+
+
+def _solver(mg, p, N, graphs, **kw):
+    old = os.environ.get("MGFEM_NO_GRAPHS")
+    os.environ["MGFEM_NO_GRAPHS"] = "0" if graphs else "1"
+    try:
+        return mg.Solver(p.psi, N, **kw)
+    finally:
+        if old is None:
+            del os.environ["MGFEM_NO_GRAPHS"]
+        else:
+            os.environ["MGFEM_NO_GRAPHS"] = old
+
+
+@pytest.mark.parametrize("kw", [{}, {"cycle": 2}, {"precision": 1}], ids=["V", "W", "mixed"])
+def test_replayed_solves_equal_eager(kw):
+    mg = _gpu()
+    N = 256
+    p = W.flower_mms(N)
+    sg = _solver(mg, p, N, True, **kw)
+    se = _solver(mg, p, N, False, **kw)
+    rng = np.random.default_rng(5)
+    for rep in range(3):
+        f = p.f * (1.0 + 0.1 * rep) + 0.01 * rng.standard_normal(p.f.shape)
+        ug, hg = sg.solve(f, p.g, tol=1e-10)
+        ue, he = se.solve(f, p.g, tol=1e-10)
+        torch.cuda.synchronize()
+        assert len(hg) == len(he)
+        assert np.array_equal(hg, he), (rep, hg, he)
+        assert torch.equal(ug, ue), rep
+        # the caller's own work between solves on the same stream
+        ug.mul_(0.0)
+    # a warm start and a fixed cycle count replay the same graphs
+    ug, hg = sg.solve(p.f, p.g, tol=-1.0, max_cycles=4, u0=ue)
+    ue2, he2 = se.solve(p.f, p.g, tol=-1.0, max_cycles=4, u0=ue)
+    assert np.array_equal(hg, he2) and torch.equal(ug, ue2)
+
+
+def test_replayed_adjoint_equals_eager():
+    mg = _gpu()
+    N = 256
+    p = W.flower_mms(N)
+    sg = _solver(mg, p, N, True)
+    se = _solver(mg, p, N, False)
+    u, _ = se.solve(p.f, p.g, tol=1e-10)
+    J, dJdu = se.misfit(u, W.adjoint_target(N))
+    for k in (3, 5, 3):
+        a = sg.adjoint(dJdu, tol=-1.0, max_cycles=k)
+        b = se.adjoint(dJdu, tol=-1.0, max_cycles=k)
+        for x, y in zip(a[:3], b[:3]):
+            assert torch.equal(x, y), k
+        assert np.array_equal(a[3], b[3])
+
+
+def test_profiled_replay_times_the_sweep():
+    """Timing events inside the replayed graph: one timed launch per finest
+    sweep, same results as the unprofiled solve."""
+    mg = _gpu()
+    N = 2048
+    p = W.flower_mms(N)
+    s = mg.Solver(p.psi, N)
+    u0, h0 = s.solve(p.f, p.g, tol=1e-10)
+    s.profile(True)
+    u1, h1 = s.solve(p.f, p.g, tol=1e-10)
+    prof = s.profile_read(0)
+    s.profile(False)
+    assert np.array_equal(h0, h1) and torch.equal(u0, u1)
+    cycles = len(h1) - 1
+    # three finest sweeps per cycle plus the speculative one of the last iteration
+    assert prof["launches"] == 3 * cycles + 1
+    assert prof["total_ms"] > 0 and prof["alg_bytes"] > 0
