@@ -35,6 +35,9 @@ namespace mgfem {
 namespace {
 
 constexpr int kHalo = 4;
+// threads of the single-workgroup coarse cycle: the levels it runs hold at
+// most a few thousand nodes, so few waves keep its many barriers cheap
+constexpr int kCoarseThreads = 256;
 
 template <class T>
 struct SweepArgs {
@@ -582,29 +585,81 @@ __device__ inline T lds_res(const WgLev<T>& L, int q) {
   return bv - (T(8) / T(3) * x[q] - nb / T(3));
 }
 
+// Gauss-Seidel value at q from a row slot and right-hand side held in registers
+template <class T>
+__device__ inline T lds_gs_reg(const WgLev<T>& L, int q, int16_t sl, T bv) {
+  const int W = L.W;
+  const T* x = L.x;
+  if (sl >= 0) {
+    const T* cf = L.coef + 10 * sl;
+    const T acc = bv - (cf[0] * x[q - W - 1] + cf[1] * x[q - W] + cf[2] * x[q - W + 1] + cf[3] * x[q - 1] +
+                        cf[4] * x[q + 1] + cf[5] * x[q + W - 1] + cf[6] * x[q + W] + cf[7] * x[q + W + 1]);
+    return acc * cf[9];
+  }
+  const T nb = (x[q - W - 1] + x[q - W] + x[q - W + 1]) + (x[q - 1] + x[q + 1]) +
+               (x[q + W - 1] + x[q + W] + x[q + W + 1]);
+  return (T(3) * bv + nb) * T(0.125);
+}
+
+// One smoothing step of a level held in LDS.  Each thread first loads, for
+// every colour of the full and the cut list, the index, row slot and
+// right-hand side of its first kWgCache nodes into registers; a colour phase
+// then only reads x and the stored coefficients (independent LDS reads) before
+// its barrier.  Nodes beyond the cached ones take the plain path.
+constexpr int kWgCache = 2;
+
 template <class T>
 __device__ void wg_smooth(const WgLev<T>& L, int eta, bool reverse) {
+  int qf[4][kWgCache], qc[4][kWgCache];
+  int16_t sf[4][kWgCache], sc[4][kWgCache];
+  T bf[4][kWgCache], bc[4][kWgCache];
+  const int bs = blockDim.x, tid = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int u = 0; u < kWgCache; ++u) {
+      const int tf = L.act_off[c] + tid + u * bs;
+      const int q = tf < L.act_off[c + 1] ? L.act[tf] : -1;
+      qf[c][u] = q;
+      sf[c][u] = q >= 0 ? L.slot[q] : (int16_t)-1;
+      bf[c][u] = q >= 0 ? L.b[q] : T(0);
+      const int tc = L.cut_off[c] + tid + u * bs;
+      const int r = tc < L.cut_off[c + 1] ? L.cut[tc] : -1;
+      qc[c][u] = r;
+      sc[c][u] = r >= 0 ? L.slot[r] : (int16_t)-1;
+      bc[c][u] = r >= 0 ? L.b[r] : T(0);
+    }
   auto full = [&](int c) {
-    for (int t = L.act_off[c] + threadIdx.x; t < L.act_off[c + 1]; t += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < kWgCache; ++u)
+      if (qf[c][u] >= 0) L.x[qf[c][u]] = lds_gs_reg<T>(L, qf[c][u], sf[c][u], bf[c][u]);
+    for (int t = L.act_off[c] + tid + kWgCache * bs; t < L.act_off[c + 1]; t += bs) {
       const int q = L.act[t];
       L.x[q] = lds_gs<T>(L, q);
     }
     __syncthreads();
   };
   auto cut = [&](int c) {
-    for (int t = L.cut_off[c] + threadIdx.x; t < L.cut_off[c + 1]; t += blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < kWgCache; ++u)
+      if (qc[c][u] >= 0) L.x[qc[c][u]] = lds_gs_reg<T>(L, qc[c][u], sc[c][u], bc[c][u]);
+    for (int t = L.cut_off[c] + tid + kWgCache * bs; t < L.cut_off[c + 1]; t += bs) {
       const int q = L.cut[t];
       L.x[q] = lds_gs<T>(L, q);
     }
     __syncthreads();
   };
   if (!reverse) {
+#pragma unroll
     for (int c = 0; c < 4; ++c) full(c);
     for (int e = 0; e < eta; ++e)
+#pragma unroll
       for (int c = 0; c < 4; ++c) cut(c);
   } else {
     for (int e = 0; e < eta; ++e)
+#pragma unroll
       for (int c = 3; c >= 0; --c) cut(c);
+#pragma unroll
     for (int c = 3; c >= 0; --c) full(c);
   }
 }
@@ -756,7 +811,7 @@ __device__ void coarse_body(const CoarseArgs<T>& a, unsigned char* base, int* sd
 }
 
 template <class T>
-__global__ __launch_bounds__(1024) void k_coarse(CoarseArgs<T> a) {
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse(CoarseArgs<T> a) {
   extern __shared__ __align__(16) unsigned char base[];
   __shared__ int sdesc[kDesc * kMaxWgLevels];
   coarse_body<T>(a, base, sdesc);
@@ -967,7 +1022,7 @@ void coarse_wg(mgfem_ctx* c, bool reverse) {
   a.reverse = reverse ? 1 : 0;
   a.gstar = c->p.cycle == MGFEM_CYCLE_W ? 2 : 1;
   const int lds = std::is_same<T, double>::value ? P.lds64 : P.lds32;
-  hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(1024), lds, c->s, a);
+  hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kCoarseThreads), lds, c->s, a);
   Lc.cur = 0;
 }
 
