@@ -96,6 +96,18 @@ struct Level {
   int* tiles = nullptr;  // sweep tiles that hold an active node
   int ntiles = 0;
   int tile_shape = -1;
+  // per sweep tile (in list order): the stored rows of its staged region
+  // (region index, the 9 coefficients) and the cut vertices of its core
+  // (region index, snapshot slot), so that a sweep reads no row and no
+  // snapshot position from global memory between its colour phases
+  int* tp_off = nullptr;  // ntiles + 1
+  int* tp_idx = nullptr;
+  double* tp_coef = nullptr;
+  float* tp_coef32 = nullptr;
+  int* tc_off = nullptr;  // ntiles + 1
+  int* tc_idx = nullptr;
+  int* tc_pos = nullptr;
+  int tp_max = 0, tc_max = 0;
   bool empty() const { return bbox[0] > bbox[1]; }
 };
 

@@ -61,6 +61,13 @@ struct SweepArgs {
   int norm;
   const T* xc;  // coarse iterate to prolongate into the staged tile, or null
   int sc;
+  // tile plan (see Level): stored rows and core cut vertices of each tile
+  const int* tp_off;
+  const int* tp_idx;
+  const T* tp_coef;
+  const int* tc_off;
+  const int* tc_idx;
+  const int* tc_pos;
 };
 
 __device__ inline double nanmax2(double a, double b) { return (b > a || b != b) ? b : a; }
@@ -76,6 +83,20 @@ __device__ inline T stored_offdiag(const T* __restrict__ A, int64_t n, int64_t k
   acc += A[6 * n + k] * su[q + RW - 1];
   acc += A[7 * n + k] * su[q + RW];
   acc += A[8 * n + k] * su[q + RW + 1];
+  return acc;
+}
+
+// the same off-diagonal product from a row kept in LDS (cf: 9 coefficients)
+template <class T, int RW>
+__device__ inline T lds_offdiag(const T* cf, const T* su, int q) {
+  T acc = cf[0] * su[q - RW - 1];
+  acc += cf[1] * su[q - RW];
+  acc += cf[2] * su[q - RW + 1];
+  acc += cf[3] * su[q - 1];
+  acc += cf[5] * su[q + 1];
+  acc += cf[6] * su[q + RW - 1];
+  acc += cf[7] * su[q + RW];
+  acc += cf[8] * su[q + RW + 1];
   return acc;
 }
 
@@ -143,7 +164,12 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   constexpr int NU = (RW * RH + BS - 1) / BS;
   constexpr int NXM = (RW - 1) / 2, NYM = (RH - 1) / 2;  // colour nodes per row/column, phase 0 bound
   constexpr int NP = (NXM * NYM + BS - 1) / BS;          // phase nodes per thread
+  constexpr int PR = 255;  // stored rows of a tile kept in LDS (slot 255: read A)
+  constexpr int NCF = (9 * PR + BS - 1) / BS, NRI = (PR + BS - 1) / BS;
+  constexpr int KC = 2;                             // core cut vertices prefetched per thread
   __shared__ T su[RH * RW];
+  __shared__ T scf[9 * PR];
+  __shared__ uint8_t sslot[RH * RW];  // stored node: its row in scf (255: read A); others unused
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
   const int t = xcd * a.per + loc;
   if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
@@ -170,6 +196,29 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
       pq[p][it] = ok ? ri + rj * RW : -1;
       pf[p][it] = ok ? a.fl[gi + (int64_t)gj * a.s] : 0;
     }
+  }
+  // the tile plan: rows of its stored nodes, its core cut vertices
+  const int p0 = a.tp_off[t], nrow = a.tp_off[t + 1] - p0;
+  const int nrl = min(nrow, PR);
+  T rcf[NCF];
+  int rix[NRI];
+#pragma unroll
+  for (int u = 0; u < NCF; ++u) {
+    const int q = tid + u * BS;
+    rcf[u] = q < 9 * nrl ? a.tp_coef[9 * (int64_t)p0 + q] : T(0);
+  }
+#pragma unroll
+  for (int u = 0; u < NRI; ++u) {
+    const int e = tid + u * BS;
+    rix[u] = e < nrl ? a.tp_idx[p0 + e] : -1;
+  }
+  const int c0 = a.tc_off[t], ncut = a.tc_off[t + 1] - c0;
+  int cix[KC], cpo[KC];
+#pragma unroll
+  for (int u = 0; u < KC; ++u) {
+    const int e = tid + u * BS;
+    cix[u] = e < ncut ? a.tc_idx[c0 + e] : -1;
+    cpo[u] = e < ncut ? a.tc_pos[c0 + e] : 0;
   }
   T ru[NU];
 #pragma unroll
@@ -201,13 +250,22 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
     const int q = tid + BS * it;
     if (q < RW * RH) su[q] = ru[it];
   }
+#pragma unroll
+  for (int u = 0; u < NCF; ++u) {
+    const int q = tid + u * BS;
+    if (q < 9 * nrl) scf[q] = rcf[u];
+  }
+#pragma unroll
+  for (int u = 0; u < NRI; ++u)
+    if (rix[u] >= 0) sslot[rix[u]] = (uint8_t)(tid + u * BS);
+  for (int e = PR + tid; e < nrow; e += BS) sslot[a.tp_idx[p0 + e]] = (uint8_t)PR;  // beyond the LDS rows
   __syncthreads();
   auto in_core = [&](int q) {
     const int ri = q % RW, rj = q / RW;
     return ri >= kHalo && ri < kHalo + TW && rj >= kHalo && rj < kHalo + TH && ox + ri <= a.i1 && oy + rj <= a.j1;
   };
   if (a.norm) {
-    __shared__ double smx[BS], ssm[BS];
+    __shared__ double smx[BS / 64], ssm[BS / 64];
     double mx = 0.0, sm = 0.0;
 #pragma unroll
     for (int p = 0; p < 4; ++p)
@@ -215,27 +273,38 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
       for (int it = 0; it < NP; ++it) {
         const int q = pq[p][it];
         if (q < 0 || !(pf[p][it] & kFlagActive) || !in_core(q)) continue;
-        const int64_t k = (ox + q % RW) + (int64_t)(oy + q / RW) * a.s;
         T ax;
-        if (pf[p][it] & kFlagStored) ax = a.A[4 * a.n + k] * su[q] + stored_offdiag<T, RW>(a.A, a.n, k, su, q);
-        else ax = T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) / T(3);
+        if (pf[p][it] & kFlagStored) {
+          const int sl = sslot[q];
+          if (sl < PR) {
+            ax = scf[9 * sl + 4] * su[q] + lds_offdiag<T, RW>(scf + 9 * sl, su, q);
+          } else {
+            const int64_t k = (ox + q % RW) + (int64_t)(oy + q / RW) * a.s;
+            ax = a.A[4 * a.n + k] * su[q] + stored_offdiag<T, RW>(a.A, a.n, k, su, q);
+          }
+        } else {
+          ax = T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) / T(3);
+        }
         const double r = (double)(pb[p][it] - ax);
         mx = nanmax2(mx, fabs(r));
         sm += r * r;
       }
-    smx[tid] = mx;
-    ssm[tid] = sm;
-    __syncthreads();
-    for (int w = BS / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        smx[tid] = nanmax2(smx[tid], smx[tid + w]);
-        ssm[tid] += ssm[tid + w];
-      }
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      mx = nanmax2(mx, __shfl_xor(mx, o));
+      sm += __shfl_xor(sm, o);
     }
+    if ((tid & 63) == 0) {
+      smx[tid >> 6] = mx;
+      ssm[tid >> 6] = sm;
+    }
+    __syncthreads();
     if (tid == 0) {
-      a.part[2 * t] = smx[0];
-      a.part[2 * t + 1] = ssm[0];
+      for (int w = 1; w < BS / 64; ++w) {
+        mx = nanmax2(mx, smx[w]);
+        sm += ssm[w];
+      }
+      a.part[2 * t] = mx;
+      a.part[2 * t + 1] = sm;
     }
   }
 #pragma unroll
@@ -246,15 +315,24 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
       const uint8_t f = pf[p][it];
       if (q < 0 || !(f & kFlagActive)) continue;
       const int64_t k = (ox + q % RW) + (int64_t)(oy + q / RW) * a.s;
-      const T v = gs_value<T, RW>(a.A, a.n, k, (f & kFlagStored) != 0, su, q, pb[p][it]);
-      su[q] = v;
-      if (in_core(q)) {
-        a.xout[k] = v;
-        if (f & kFlagCut) a.snap[a.cutpos[k]] = v;
+      T v;
+      if (f & kFlagStored) {
+        const int sl = sslot[q];
+        v = sl < PR ? (pb[p][it] - lds_offdiag<T, RW>(scf + 9 * sl, su, q)) / scf[9 * sl + 4]
+                    : gs_value<T, RW>(a.A, a.n, k, true, su, q, pb[p][it]);
+      } else {
+        v = gs_value<T, RW>(a.A, a.n, k, false, su, q, pb[p][it]);
       }
+      su[q] = v;
+      if (in_core(q)) a.xout[k] = v;
     }
     __syncthreads();
   }
+  // snapshot of the core's cut vertices (final after their colour's phase)
+#pragma unroll
+  for (int u = 0; u < KC; ++u)
+    if (cix[u] >= 0) a.snap[cpo[u]] = su[cix[u]];
+  for (int e = tid + KC * BS; e < ncut; e += BS) a.snap[a.tc_pos[c0 + e]] = su[a.tc_idx[c0 + e]];
 }
 
 // extra smoothing of one group of cut vertices, all phases in LDS
@@ -873,14 +951,20 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   a.j1 = L.bbox[3];
   a.ntx = (a.i1 - a.i0 + TW) / TW;
   a.nty = (a.j1 - a.j0 + TH) / TH;
-  a.tiles = nullptr;
-  a.ntiles = a.ntx * a.nty;
-  if (L.tile_shape == shape && L.tiles) {
-    a.tiles = L.tiles;
-    a.ntiles = L.ntiles;
-  }
+  // the tile list and its plans exist for every level with a smoother, in
+  // the shape sweep_shape() gives
+  a.tiles = L.tiles;
+  a.ntiles = L.ntiles;
+  (void)shape;
   a.per = (a.ntiles + 7) / 8;
   a.reverse = reverse ? 1 : 0;
+  a.tp_off = L.tp_off;
+  a.tp_idx = L.tp_idx;
+  a.tp_coef = std::is_same<T, double>::value ? reinterpret_cast<const T*>(L.tp_coef)
+                                             : reinterpret_cast<const T*>(L.tp_coef32);
+  a.tc_off = L.tc_off;
+  a.tc_idx = L.tc_idx;
+  a.tc_pos = L.tc_pos;
   if (c->prof.on && std::is_same<T, double>::value && l == 0) {
     // algorithmic bytes: per active row x read and written, b read, its flag,
     // the 72 bytes of a stored row; a fused prolongation also reads x_c
@@ -1081,10 +1165,61 @@ __global__ void k_tile_active(const uint8_t* __restrict__ fl, int s, int i0, int
   if (threadIdx.x == 0) act[t] = any;
 }
 
+// Tile plan of one sweep tile (one block per tile in list order): the stored
+// rows of its phase-0 box (the staged region less its outer ring) and the cut
+// vertices of its core.  fill = 0 counts, fill = 1 writes the entries at the
+// offsets (order within a tile is free: updates of one colour are independent).
+__global__ void k_tile_plan(const uint8_t* __restrict__ fl, const double* __restrict__ A,
+                            const float* __restrict__ A32, int64_t n, const int* __restrict__ cutpos, int N, int s,
+                            int i0, int j0, int i1, int j1, int TW, int TH, int ntx,
+                            const int* __restrict__ tiles, int fill, int* __restrict__ cnt,
+                            int* __restrict__ ccnt, const int* __restrict__ off, const int* __restrict__ coff,
+                            int* __restrict__ idx, double* __restrict__ coef, float* __restrict__ coef32,
+                            int* __restrict__ cidx, int* __restrict__ cpos) {
+  __shared__ int nr, nc;
+  if (threadIdx.x == 0) nr = nc = 0;
+  __syncthreads();
+  const int t = blockIdx.x;
+  const int tile = tiles[t];
+  const int RW = TW + 2 * kHalo, RH = TH + 2 * kHalo;
+  const int ox = i0 + (tile % ntx) * TW - kHalo, oy = j0 + (tile / ntx) * TH - kHalo;
+  for (int q = threadIdx.x; q < RW * RH; q += blockDim.x) {
+    const int ri = q % RW, rj = q / RW;
+    const int gi = ox + ri, gj = oy + rj;
+    if (ri < 1 || rj < 1 || ri >= RW - 1 || rj >= RH - 1 || gi < 0 || gj < 0 || gi > N || gj > N) continue;
+    const int64_t k = gi + (int64_t)gj * s;
+    const uint8_t f = fl[k];
+    if ((f & kFlagActive) && (f & kFlagStored)) {
+      const int e = atomicAdd(&nr, 1);
+      if (fill) {
+        const int64_t w = off[t] + e;
+        idx[w] = q;
+        for (int p = 0; p < 9; ++p) coef[9 * w + p] = A[p * n + k];
+        if (coef32)
+          for (int p = 0; p < 9; ++p) coef32[9 * w + p] = A32[p * n + k];
+      }
+    }
+    const bool core = ri >= kHalo && ri < kHalo + TW && rj >= kHalo && rj < kHalo + TH && gi <= i1 && gj <= j1;
+    if (core && (f & kFlagCut)) {
+      const int e = atomicAdd(&nc, 1);
+      if (fill) {
+        cidx[coff[t] + e] = q;
+        cpos[coff[t] + e] = cutpos[k];
+      }
+    }
+  }
+  __syncthreads();
+  if (!fill && threadIdx.x == 0) {
+    cnt[t] = nr;
+    ccnt[t] = nc;
+  }
+}
+
 int build_tile_lists(mgfem_ctx* c) {
-  for (int l = 0; l < (int)c->lv.size(); ++l) {
+  const int nl = (int)c->lv.size();
+  for (int l = 0; l + 1 < nl; ++l) {  // every level with a smoother
     Level& L = c->lv[l];
-    if (L.empty() || (c->cplan.lc >= 0 && l >= c->cplan.lc)) continue;
+    if (L.empty()) continue;
     const int shape = sweep_shape(c, l);
     const int TW = shape == kShapeFinest ? 64 : (shape == kShapeLarge ? 64 : 32);
     const int TH = shape == kShapeFinest ? 64 : (shape == kShapeLarge ? 32 : 16);
@@ -1104,6 +1239,42 @@ int build_tile_lists(mgfem_ctx* c) {
       MGFEM_HIP_TRY(hipMemcpyAsync(L.tiles, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice, c->s));
     L.ntiles = (int)list.size();
     L.tile_shape = shape;
+    // tile plans: count, offsets, fill
+    const int nt = L.ntiles;
+    int *cnt = nullptr, *ccnt = nullptr;
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &cnt, std::max(1, nt)));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &ccnt, std::max(1, nt)));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tp_off, nt + 1));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tc_off, nt + 1));
+    if (nt > 0)
+      hipLaunchKernelGGL(k_tile_plan, dim3(nt), dim3(256), 0, c->s, L.flags, L.A, L.A32, L.n, L.cutpos, L.N,
+                         L.stride, L.bbox[0], L.bbox[2], L.bbox[1], L.bbox[3], TW, TH, ntx, L.tiles, 0, cnt, ccnt,
+                         nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    MGFEM_HIP_TRY(hipGetLastError());
+    std::vector<int> hc(std::max(1, nt)), hcc(std::max(1, nt)), ho(nt + 1), hco(nt + 1);
+    MGFEM_HIP_TRY(hipMemcpyAsync(hc.data(), cnt, hc.size() * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    MGFEM_HIP_TRY(hipMemcpyAsync(hcc.data(), ccnt, hcc.size() * sizeof(int), hipMemcpyDeviceToHost, c->s));
+    MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+    ho[0] = hco[0] = 0;
+    L.tp_max = L.tc_max = 0;
+    for (int q = 0; q < nt; ++q) {
+      ho[q + 1] = ho[q] + hc[q];
+      hco[q + 1] = hco[q] + hcc[q];
+      L.tp_max = std::max(L.tp_max, hc[q]);
+      L.tc_max = std::max(L.tc_max, hcc[q]);
+    }
+    MGFEM_HIP_TRY(hipMemcpyAsync(L.tp_off, ho.data(), ho.size() * sizeof(int), hipMemcpyHostToDevice, c->s));
+    MGFEM_HIP_TRY(hipMemcpyAsync(L.tc_off, hco.data(), hco.size() * sizeof(int), hipMemcpyHostToDevice, c->s));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tp_idx, std::max(1, ho[nt])));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tp_coef, 9 * (size_t)std::max(1, ho[nt])));
+    if (L.A32) MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tp_coef32, 9 * (size_t)std::max(1, ho[nt])));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tc_idx, std::max(1, hco[nt])));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tc_pos, std::max(1, hco[nt])));
+    if (nt > 0)
+      hipLaunchKernelGGL(k_tile_plan, dim3(nt), dim3(256), 0, c->s, L.flags, L.A, L.A32, L.n, L.cutpos, L.N,
+                         L.stride, L.bbox[0], L.bbox[2], L.bbox[1], L.bbox[3], TW, TH, ntx, L.tiles, 1, nullptr,
+                         nullptr, L.tp_off, L.tc_off, L.tp_idx, L.tp_coef, L.tp_coef32, L.tc_idx, L.tc_pos);
+    MGFEM_HIP_TRY(hipGetLastError());
   }
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   return MGFEM_OK;
