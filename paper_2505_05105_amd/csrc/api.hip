@@ -269,7 +269,8 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
   SETUP_TRY(ctx_alloc_t(c, &c->F64tmp, n0));
   SETUP_TRY(ctx_alloc_t(c, &c->zero, n0));
   SETUP_TRY(ctx_alloc_t(c, &c->lam, n0));
-  SETUP_TRY(ctx_alloc_t(c, &c->red_partial, 2 * kRedBlocks));
+  // one (max, sum) pair per block of the level-0 box kernels (256 x 4 nodes)
+  SETUP_TRY(ctx_alloc_t(c, &c->red_partial, 2 * red_pairs(N)));
   SETUP_TRY(ctx_alloc_t(c, &c->red_out, 2));
   SETUP_TRY(ctx_alloc_t(c, &c->red_seq_dev, 1));
   SETUP_TRY(ctx_alloc_t(c, &c->sweep_counter, 1));
@@ -307,6 +308,8 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
   }
   c->coarse_n = st.coarse_n;
   rc = build_plans(c);
+  if (rc != MGFEM_OK) return bail(rc);
+  rc = build_cut_rows(c);
   if (rc != MGFEM_OK) return bail(rc);
   SETUP_TRY(hipStreamSynchronize(c->s));
   mgfem_info& I = c->info;
@@ -638,8 +641,8 @@ int mgfem_adjoint(mgfem_handle c, const double* dJdu_dev, double rel_tol, int32_
   int rc = iterate(c, lam, c->F, rel_tol, max_cycles, true, false, false, -1.0, res_hist_host, &nc);
   if (n_cycles) *n_cycles = nc;
   if (rc != MGFEM_OK && rc != MGFEM_ERR_NOT_CONVERGED) return rc;
-  if (dJdf_dev) launch_stencil_apply(c, c->M, lam, dJdf_dev, false);
-  if (dJdg_dev) launch_stencil_apply(c, c->G, lam, dJdg_dev, true);
+  if (dJdf_dev) launch_mass_apply(c, lam, dJdf_dev);
+  if (dJdg_dev) launch_gt_apply(c, lam, dJdg_dev);
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   return rc;
@@ -652,7 +655,7 @@ int mgfem_misfit(mgfem_handle c, const double* u_dev, const double* ut_dev, doub
   double* e = c->F64tmp;
   double* Me = dJdu_dev ? dJdu_dev : c->lam;
   launch_sub_active(c, e, u_dev, ut_dev);
-  launch_stencil_apply(c, c->M, e, Me, false);
+  launch_mass_apply(c, e, Me);
   launch_dot_reduce(c, e, Me);
   MGFEM_HIP_TRY(hipGetLastError());
   double mx, l2, sum;

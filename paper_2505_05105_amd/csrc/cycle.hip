@@ -11,6 +11,11 @@ namespace mgfem {
 namespace {
 
 
+// the box kernels below run 256 x 4 nodes per block (a thread takes one
+// column of four rows), so that every thread has four independent load chains
+// in flight; block (x, y) writes the partial pair x + y * gridDim.x
+constexpr int kNodesPerThread = 4;
+
 // max that propagates NaN (so a diverged solve is reported, not hidden)
 __device__ inline double nanmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
@@ -54,175 +59,277 @@ __device__ inline T row_times_x(const LevelView<T>& v, int i, int j, int64_t k, 
   return diag * x[k] - nb / T(3);
 }
 
-// residual norms of level 0: per-block max |r| and sum r^2 (fixed block count,
-// fixed order: deterministic); optionally stores r
-__global__ void k_resnorm_partial(LevelView<double> v, const double* __restrict__ F, double* r_out,
-                                  int i0, int j0, int ni, int nj, double* __restrict__ part) {
-  __shared__ double smax[256], ssum[256];
+// per-block (max |v|, sum v^2) of a block of 256 threads into part[2 b],
+// part[2 b + 1]: a wave reduction, then the four waves in a fixed order
+__device__ inline void block_pair(double mx, double sm, double* __restrict__ part) {
+  __shared__ double smax[4], ssum[4];
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = nanmax(mx, __shfl_xor(mx, o));
+    sm += __shfl_xor(sm, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smax[threadIdx.x >> 6] = mx;
+    ssum[threadIdx.x >> 6] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      mx = nanmax(mx, smax[w]);
+      sm += ssum[w];
+    }
+    const int b = blockIdx.x + blockIdx.y * gridDim.x;
+    part[2 * b] = mx;
+    part[2 * b + 1] = sm;
+  }
+}
+
+// A block of the box kernels owns 256 x 4 nodes; the values its stencils read
+// are staged in LDS with a halo of one (zero off the grid), every global load
+// of the staging issued before the first is used.
+constexpr int kBX = 256, kBY = kNodesPerThread, kSW = kBX + 2, kSH = kBY + 2, kSN = kSW * kSH;
+
+template <class Load>
+__device__ inline void stage_box(double* __restrict__ sv, int bi, int bj, int N, int s, Load load) {
+  constexpr int NU = (kSN + 255) / 256;
+  double r[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int q = threadIdx.x + u * 256;
+    const int gi = bi - 1 + q % kSW, gj = bj - 1 + q / kSW;
+    const bool in = q < kSN && gi >= 0 && gj >= 0 && gi <= N && gj <= N;
+    r[u] = in ? load(gi + (int64_t)gj * s) : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int q = threadIdx.x + u * 256;
+    if (q < kSN) sv[q] = r[u];
+  }
+  __syncthreads();
+}
+
+__device__ inline double box_neighbours(const double* sv, int q) {
+  return (sv[q - kSW - 1] + sv[q - kSW] + sv[q - kSW + 1]) + (sv[q - 1] + sv[q + 1]) +
+         (sv[q + kSW - 1] + sv[q + kSW] + sv[q + kSW + 1]);
+}
+
+// stored row times the staged values (the row's off-grid coefficients are zero)
+__device__ inline double box_row(const double* __restrict__ A, int64_t n, int64_t k, const double* sv, int q) {
+  double acc = A[4 * n + k] * sv[q];
+  acc += A[k] * sv[q - kSW - 1];
+  acc += A[n + k] * sv[q - kSW];
+  acc += A[2 * n + k] * sv[q - kSW + 1];
+  acc += A[3 * n + k] * sv[q - 1];
+  acc += A[5 * n + k] * sv[q + 1];
+  acc += A[6 * n + k] * sv[q + kSW - 1];
+  acc += A[7 * n + k] * sv[q + kSW];
+  acc += A[8 * n + k] * sv[q + kSW + 1];
+  return acc;
+}
+
+// residual norms of level 0: per-block max |r| and sum r^2 (one node per
+// thread, partials in block order: deterministic); optionally stores r
+__global__ __launch_bounds__(256) void k_resnorm_partial(LevelView<double> v, const double* __restrict__ F,
+                                                         double* r_out, int i0, int j0, int ni, int nj,
+                                                         double* __restrict__ part) {
+  __shared__ double sv[kSN];
+  const int bi = i0 + blockIdx.x * kBX, bj = j0 + blockIdx.y * kBY;
+  const double* x = v.x;
+  stage_box(sv, bi, bj, v.N, v.s, [&](int64_t k) { return x[k]; });
   double mx = 0.0, sm = 0.0;
-  const int64_t tot = (int64_t)ni * nj;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int i = i0 + (int)(t % ni), j = j0 + (int)(t / ni);
+  const int i = bi + threadIdx.x;
+#pragma unroll
+  for (int rep = 0; rep < kBY; ++rep) {
+    const int j = bj + rep;
+    if (i >= i0 + ni || j >= j0 + nj) continue;
     const int64_t k = i + (int64_t)j * v.s;
     const uint8_t f = v.fl[k];
     if (!(f & kFlagActive)) continue;
-    double diag;
-    const double r = F[k] - row_times_x(v, i, j, k, f, diag);
+    const int q = threadIdx.x + 1 + (rep + 1) * kSW;
+    const double ax = (f & kFlagStored) ? box_row(v.A, v.n, k, sv, q)
+                                        : 8.0 / 3.0 * sv[q] - box_neighbours(sv, q) / 3.0;
+    const double r = F[k] - ax;
     if (r_out) r_out[k] = r;
     mx = nanmax(mx, fabs(r));
     sm += r * r;
   }
-  smax[threadIdx.x] = mx;
-  ssum[threadIdx.x] = sm;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      smax[threadIdx.x] = nanmax(smax[threadIdx.x], smax[threadIdx.x + w]);
-      ssum[threadIdx.x] += ssum[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = smax[0];
-    part[2 * blockIdx.x + 1] = ssum[0];
-  }
+  block_pair(mx, sm, part);
 }
 
 __global__ void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
                               double* __restrict__ part) {
-  __shared__ double ssum[256];
   double sm = 0.0;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
        t += (int64_t)gridDim.x * blockDim.x)
     sm += a[t] * b[t];
-  ssum[threadIdx.x] = sm;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) ssum[threadIdx.x] += ssum[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = 0.0;
-    part[2 * blockIdx.x + 1] = ssum[0];
-  }
+  block_pair(0.0, sm, part);
 }
 
-__global__ void k_reduce_final(const double* __restrict__ part, int nb, double* __restrict__ out,
-                               double* host_out, double* seq) {
-  __shared__ double smax[256], ssum[256];
+__global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ part, int nb,
+                                                      double* __restrict__ out, double* host_out, double* seq) {
+  __shared__ double smax[16], ssum[16];
   double mx = 0.0, sm = 0.0;
   for (int t = threadIdx.x; t < nb; t += blockDim.x) {
     mx = nanmax(mx, part[2 * t]);
     sm += part[2 * t + 1];
   }
-  smax[threadIdx.x] = mx;
-  ssum[threadIdx.x] = sm;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      smax[threadIdx.x] = nanmax(smax[threadIdx.x], smax[threadIdx.x + w]);
-      ssum[threadIdx.x] += ssum[threadIdx.x + w];
-    }
-    __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = nanmax(mx, __shfl_xor(mx, o));
+    sm += __shfl_xor(sm, o);
   }
+  if ((threadIdx.x & 63) == 0) {
+    smax[threadIdx.x >> 6] = mx;
+    ssum[threadIdx.x >> 6] = sm;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    out[0] = smax[0];
-    out[1] = ssum[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      mx = nanmax(mx, smax[w]);
+      sm += ssum[w];
+    }
+    out[0] = mx;
+    out[1] = sm;
     // straight to pinned host memory; the sequence number (counted on the
     // device, so a replayed graph still numbers its reductions) goes last
     const double q = seq[0] + 1.0;
     seq[0] = q;
-    host_out[0] = smax[0];
-    host_out[1] = ssum[0];
+    host_out[0] = mx;
+    host_out[1] = sm;
     __threadfence_system();
     host_out[2] = q;
     __threadfence_system();
   }
 }
 
-// y = S x (or S^T x) for a 9-plane stencil S on the fine grid
-__global__ void k_stencil_apply(const double* __restrict__ S, const double* __restrict__ x,
-                                double* __restrict__ y, int N, int transpose) {
+// F = M f + G g (section 2, the discrete load) in two parts.  The vertices of
+// cut cells (the rows that differ from the interior ones) take their M and G
+// rows from one contiguous gathered array (18 values per vertex, in cut-list
+// order): k_cut_rows.  Every other node of the box of active nodes is done by
+// k_rhs: an active row whose four cells are interior has the constant Q1 mass
+// stencil h^2/36 [1 4 1; 4 16 4; 1 4 1] and no boundary term; k_rhs also
+// reduces (max |F|, sum F^2) over all active nodes, reading F at the cut
+// vertices, so k_cut_rows runs first.
+__global__ void k_cut_rows(const int* __restrict__ cut_list, int ncut, const double* __restrict__ rows,
+                           const double* __restrict__ x, const double* __restrict__ g, double* __restrict__ y,
+                           int N) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncut) return;
   const int s = N + 1;
-  const int64_t n = (int64_t)s * s;
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= n) return;
+  const int64_t k = cut_list[t];
+  const int i = (int)(k % s), j = (int)(k / s);
+  const double* r = rows + 18 * (int64_t)t;
+  double acc = 0.0;
+  for (int p = 0; p < 9; ++p) {
+    const int ii = i + p % 3 - 1, jj = j + p / 3 - 1;
+    if (ii < 0 || jj < 0 || ii > N || jj > N) continue;
+    const int64_t kk = ii + (int64_t)jj * s;
+    const double m = r[p], gg = r[9 + p];
+    if (m != 0.0) acc += m * x[kk];
+    if (g && gg != 0.0) acc += gg * g[kk];
+  }
+  y[k] = acc;
+}
+
+// y = G^T x at the vertices of cut cells (G couples only vertices of one cut
+// cell, so G^T x vanishes elsewhere): the coefficient of column k in row kk
+// is plane 8 - p of row kk, found through the row's cut-list position
+__global__ void k_cut_rows_gt(const int* __restrict__ cut_list, int ncut, const int* __restrict__ cutpos,
+                              const double* __restrict__ rows, const double* __restrict__ x,
+                              double* __restrict__ y, int N) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncut) return;
+  const int s = N + 1;
+  const int64_t k = cut_list[t];
   const int i = (int)(k % s), j = (int)(k / s);
   double acc = 0.0;
   for (int p = 0; p < 9; ++p) {
-    const int dx = p % 3 - 1, dy = p / 3 - 1;
-    const int ii = i + dx, jj = j + dy;
+    const int ii = i + p % 3 - 1, jj = j + p / 3 - 1;
     if (ii < 0 || jj < 0 || ii > N || jj > N) continue;
     const int64_t kk = ii + (int64_t)jj * s;
-    // row k, column kk uses plane p at k; the transpose reads row kk's
-    // coefficient of column k, i.e. plane (8 - p) at kk
-    const double a = transpose ? S[(8 - p) * n + kk] : S[p * n + k];
+    const int q = cutpos[kk];
+    if (q < 0) continue;
+    const double a = rows[18 * (int64_t)q + 9 + (8 - p)];
     if (a != 0.0) acc += a * x[kk];
   }
   y[k] = acc;
 }
 
-// per-block (max |v|, sum v^2) of a block of 256 threads into part[2 b], part[2 b + 1]
-__device__ inline void block_pair(double mx, double sm, double* __restrict__ part) {
-  __shared__ double smax[256], ssum[256];
-  smax[threadIdx.x] = mx;
-  ssum[threadIdx.x] = sm;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      smax[threadIdx.x] = nanmax(smax[threadIdx.x], smax[threadIdx.x + w]);
-      ssum[threadIdx.x] += ssum[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = smax[0];
-    part[2 * blockIdx.x + 1] = ssum[0];
-  }
+__device__ inline double mass_row(const double* sv, int q, double hh36) {
+  const double corners = (sv[q - kSW - 1] + sv[q - kSW + 1]) + (sv[q + kSW - 1] + sv[q + kSW + 1]);
+  const double edges = (sv[q - kSW] + sv[q + kSW]) + (sv[q - 1] + sv[q + 1]);
+  return hh36 * (16.0 * sv[q] + 4.0 * edges + corners);
 }
 
-// F = M f + G g on the box of active nodes (section 2, the discrete load):
-// a row whose four cells are interior has the constant Q1 mass stencil
-// h^2/36 [1 4 1; 4 16 4; 1 4 1] and no boundary term; other rows read their
-// stored M and G planes.  Also reduces (max |F|, sum F^2).
-__global__ void k_rhs(const double* __restrict__ M, const double* __restrict__ G,
-                      const uint8_t* __restrict__ fl, const double* __restrict__ f,
-                      const double* __restrict__ g, double* __restrict__ F, int N, double hh36, int i0,
-                      int j0, int ni, int nj, double* __restrict__ part) {
+// a stored row that is not a cut-cell vertex (none arise from the assembly;
+// kept so that every row is covered): from the full planes
+__device__ inline double plane_row(const double* __restrict__ S, const double* __restrict__ x, int64_t n,
+                                   int64_t k, int i, int j, int N, int s) {
+  double acc = 0.0;
+  for (int p = 0; p < 9; ++p) {
+    const int ii = i + p % 3 - 1, jj = j + p / 3 - 1;
+    if (ii < 0 || jj < 0 || ii > N || jj > N) continue;
+    const double a = S[p * n + k];
+    if (a != 0.0) acc += a * x[ii + (int64_t)jj * s];
+  }
+  return acc;
+}
+
+__global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ M, const double* __restrict__ G,
+                                             const uint8_t* __restrict__ fl, const double* __restrict__ f,
+                                             const double* __restrict__ g, double* __restrict__ F, int N,
+                                             double hh36, int i0, int j0, int ni, int nj,
+                                             double* __restrict__ part) {
+  __shared__ double sv[kSN];
   const int s = N + 1;
   const int64_t n = (int64_t)s * s;
-  const int64_t tot = (int64_t)ni * nj;
+  const int bi = i0 + blockIdx.x * kBX, bj = j0 + blockIdx.y * kBY;
+  stage_box(sv, bi, bj, N, s, [&](int64_t k) { return f[k]; });
   double mx = 0.0, sm = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int i = i0 + (int)(t % ni), j = j0 + (int)(t / ni);
+  const int i = bi + threadIdx.x;
+#pragma unroll
+  for (int rep = 0; rep < kBY; ++rep) {
+    const int j = bj + rep;
+    if (i >= i0 + ni || j >= j0 + nj) continue;
     const int64_t k = i + (int64_t)j * s;
     const uint8_t fk = fl[k];
     double acc = 0.0;
-    if (!(fk & kFlagActive)) {
-      F[k] = 0.0;
-      continue;
+    if (fk & kFlagActive) {
+      if (!(fk & kFlagStored)) acc = mass_row(sv, threadIdx.x + 1 + (rep + 1) * kSW, hh36);
+      else if (fk & kFlagCut) acc = F[k];  // from k_cut_rows
+      else acc = plane_row(M, f, n, k, i, j, N, s) + plane_row(G, g, n, k, i, j, N, s);
     }
-    if (!(fk & kFlagStored)) {
-      const double corners = (f[k - s - 1] + f[k - s + 1]) + (f[k + s - 1] + f[k + s + 1]);
-      const double edges = (f[k - s] + f[k + s]) + (f[k - 1] + f[k + 1]);
-      acc = hh36 * (16.0 * f[k] + 4.0 * edges + corners);
-    } else {
-      for (int p = 0; p < 9; ++p) {
-        const int ii = i + p % 3 - 1, jj = j + p / 3 - 1;
-        if (ii < 0 || jj < 0 || ii > N || jj > N) continue;
-        const int64_t kk = ii + (int64_t)jj * s;
-        const double m = M[p * n + k], gg = G[p * n + k];
-        if (m != 0.0) acc += m * f[kk];
-        if (gg != 0.0) acc += gg * g[kk];
-      }
-    }
-    F[k] = acc;
+    if (!(fk & kFlagActive) || !(fk & kFlagStored) || !(fk & kFlagCut)) F[k] = acc;
     mx = nanmax(mx, fabs(acc));
     sm += acc * acc;
   }
   block_pair(mx, sm, part);
+}
+
+// y = M x on the whole grid (zero off the box of active nodes and at inactive
+// nodes); the rows of cut-cell vertices are left to k_cut_rows
+__global__ __launch_bounds__(256) void k_mass_grid(const double* __restrict__ M, const uint8_t* __restrict__ fl,
+                                                   const double* __restrict__ x, double* __restrict__ y, int N,
+                                                   double hh36, int i0, int j0, int i1, int j1) {
+  __shared__ double sv[kSN];
+  const int s = N + 1;
+  const int64_t n = (int64_t)s * s;
+  const int bi = blockIdx.x * kBX, bj = blockIdx.y * kBY;
+  const bool touches = bi <= i1 && bi + kBX - 1 >= i0 && bj <= j1 && bj + kBY - 1 >= j0;  // uniform
+  if (touches) stage_box(sv, bi, bj, N, s, [&](int64_t k) { return x[k]; });
+  const int i = bi + threadIdx.x;
+#pragma unroll
+  for (int rep = 0; rep < kBY; ++rep) {
+    const int j = bj + rep;
+    if (i > N || j > N) continue;
+    const int64_t k = i + (int64_t)j * s;
+    if (!touches || i < i0 || i > i1 || j < j0 || j > j1) {
+      y[k] = 0.0;
+      continue;
+    }
+    const uint8_t fk = fl[k];
+    if (!(fk & kFlagActive)) y[k] = 0.0;
+    else if (!(fk & kFlagStored)) y[k] = mass_row(sv, threadIdx.x + 1 + (rep + 1) * kSW, hh36);
+    else if (!(fk & kFlagCut)) y[k] = plane_row(M, x, n, k, i, j, N, s);
+  }
 }
 
 // Outer step of the mixed-precision solve, on the box of active nodes:
@@ -230,43 +337,28 @@ __global__ void k_rhs(const double* __restrict__ M, const double* __restrict__ G
 // float64, the float copy of r as the next inner right-hand side, a zero
 // float start iterate for the next inner cycle, and (max |r|, sum r^2).
 // u_new goes to a second buffer, so every thread reads the old u.
-__global__ void k_outer(LevelView<double> v, const double* __restrict__ F, const double* __restrict__ u,
-                        const float* __restrict__ e, double* __restrict__ u_out, float* __restrict__ r32,
-                        float* __restrict__ z32, int i0, int j0, int ni, int nj, double* __restrict__ part) {
-  const int64_t tot = (int64_t)ni * nj;
-  const int s = v.s;
+__global__ __launch_bounds__(256) void k_outer(LevelView<double> v, const double* __restrict__ F,
+                                               const double* __restrict__ u, const float* __restrict__ e,
+                                               double* __restrict__ u_out, float* __restrict__ r32,
+                                               float* __restrict__ z32, int i0, int j0, int ni, int nj,
+                                               double* __restrict__ part) {
+  __shared__ double sv[kSN];
+  const int bi = i0 + blockIdx.x * kBX, bj = j0 + blockIdx.y * kBY;
+  if (e) stage_box(sv, bi, bj, v.N, v.s, [&](int64_t k) { return u[k] + (double)e[k]; });
+  else stage_box(sv, bi, bj, v.N, v.s, [&](int64_t k) { return u[k]; });
   double mx = 0.0, sm = 0.0;
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < tot;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    const int i = i0 + (int)(t % ni), j = j0 + (int)(t / ni);
-    const int64_t k = i + (int64_t)j * s;
+  const int i = bi + threadIdx.x;
+#pragma unroll
+  for (int rep = 0; rep < kBY; ++rep) {
+    const int j = bj + rep;
+    if (i >= i0 + ni || j >= j0 + nj) continue;
+    const int64_t k = i + (int64_t)j * v.s;
     const uint8_t f = v.fl[k];
     if (!(f & kFlagActive)) continue;
-    auto un = [&](int64_t q) { return e ? u[q] + (double)e[q] : u[q]; };
-    const double uk = un(k);
-    double ax;
-    if (f & kFlagStored) {
-      const double* A = v.A;
-      const int64_t n = v.n;
-      ax = A[4 * n + k] * uk;
-      const bool w = i > 0, ea = i < v.N, so = j > 0, no = j < v.N;
-      if (so) {
-        if (w) ax += A[k] * un(k - s - 1);
-        ax += A[n + k] * un(k - s);
-        if (ea) ax += A[2 * n + k] * un(k - s + 1);
-      }
-      if (w) ax += A[3 * n + k] * un(k - 1);
-      if (ea) ax += A[5 * n + k] * un(k + 1);
-      if (no) {
-        if (w) ax += A[6 * n + k] * un(k + s - 1);
-        ax += A[7 * n + k] * un(k + s);
-        if (ea) ax += A[8 * n + k] * un(k + s + 1);
-      }
-    } else {
-      const double nb = (un(k - s - 1) + un(k - s) + un(k - s + 1)) + (un(k - 1) + un(k + 1)) +
-                        (un(k + s - 1) + un(k + s) + un(k + s + 1));
-      ax = 8.0 / 3.0 * uk - nb / 3.0;
-    }
+    const int q = threadIdx.x + 1 + (rep + 1) * kSW;
+    const double uk = sv[q];
+    const double ax = (f & kFlagStored) ? box_row(v.A, v.n, k, sv, q)
+                                        : 8.0 / 3.0 * uk - box_neighbours(sv, q) / 3.0;
     const double r = F[k] - ax;
     if (u_out) u_out[k] = uk;
     r32[k] = (float)r;
@@ -299,13 +391,17 @@ inline unsigned nblk(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); 
 
 void launch_rhs(mgfem_ctx* c, const double* f, const double* g, double* F) {
   const Level& L = c->lv[0];
+  const int ncut = L.cut_off[4];
+  if (ncut > 0)
+    hipLaunchKernelGGL(k_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->cut_rows, f, g,
+                       F, c->N);
   const int ni = L.bbox[1] - L.bbox[0] + 1, nj = L.bbox[3] - L.bbox[2] + 1;
-  const int64_t tot = (int64_t)ni * nj;
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (tot + 255) / 256));
-  hipLaunchKernelGGL(k_rhs, dim3(nb), dim3(256), 0, c->s, c->M, c->G, L.flags, f, g, F, c->N,
+  const dim3 grid((unsigned)std::max(1, (ni + 255) / 256), (unsigned)std::max(1, (nj + 3) / 4));
+  const int nb = (int)(grid.x * grid.y);
+  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, c->s, c->M, c->G, L.flags, f, g, F, c->N,
                      c->h * c->h / 36.0, L.bbox[0], L.bbox[2], ni, nj, c->red_partial);
   c->red_seq += 1.0;
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
                      c->red_seq_dev);
 }
 
@@ -313,19 +409,59 @@ void launch_outer(mgfem_ctx* c, const double* u, const float* e, double* u_out, 
   Level& L = c->lv[0];
   LevelView<double> v{L.A, L.flags, nullptr, nullptr, nullptr, L.N, L.stride, L.n};
   const int ni = L.bbox[1] - L.bbox[0] + 1, nj = L.bbox[3] - L.bbox[2] + 1;
-  const int64_t tot = (int64_t)ni * nj;
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (tot + 255) / 256));
-  hipLaunchKernelGGL(k_outer, dim3(nb), dim3(256), 0, c->s, v, (const double*)L.b, u, e, u_out, r32, z32,
+  const dim3 grid((unsigned)std::max(1, (ni + 255) / 256), (unsigned)std::max(1, (nj + 3) / 4));
+  const int nb = (int)(grid.x * grid.y);
+  hipLaunchKernelGGL(k_outer, grid, dim3(256), 0, c->s, v, (const double*)L.b, u, e, u_out, r32, z32,
                      L.bbox[0], L.bbox[2], ni, nj, c->red_partial);
   c->red_seq += 1.0;
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
                      c->red_seq_dev);
 }
 
-void launch_stencil_apply(mgfem_ctx* c, const double* planes, const double* x, double* y, bool transpose) {
-  const int64_t n = c->lv[0].n;
-  hipLaunchKernelGGL(k_stencil_apply, dim3(nblk(n, 256)), dim3(256), 0, c->s, planes, x, y, c->N,
-                     transpose ? 1 : 0);
+namespace {
+// the M and G rows of every cut-cell vertex of level 0, in cut-list order
+__global__ void k_gather_cut_rows(const int* __restrict__ cut_list, int ncut, const double* __restrict__ M,
+                                  const double* __restrict__ G, int64_t n, double* __restrict__ rows) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncut) return;
+  const int64_t k = cut_list[t];
+  for (int p = 0; p < 9; ++p) {
+    rows[18 * (int64_t)t + p] = M[p * n + k];
+    rows[18 * (int64_t)t + 9 + p] = G[p * n + k];
+  }
+}
+}  // namespace
+
+int build_cut_rows(mgfem_ctx* c) {
+  const Level& L = c->lv[0];
+  const int ncut = L.cut_off[4];
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cut_rows, 18 * (size_t)std::max(1, ncut)));
+  if (ncut > 0)
+    hipLaunchKernelGGL(k_gather_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->M, c->G,
+                       L.n, c->cut_rows);
+  MGFEM_HIP_TRY(hipGetLastError());
+  return MGFEM_OK;
+}
+
+void launch_mass_apply(mgfem_ctx* c, const double* x, double* y) {
+  const Level& L = c->lv[0];
+  const int N = c->N;
+  const dim3 grid((unsigned)((N + 1 + kBX - 1) / kBX), (unsigned)((N + 1 + kBY - 1) / kBY));
+  hipLaunchKernelGGL(k_mass_grid, grid, dim3(256), 0, c->s, c->M, L.flags, x, y, N, c->h * c->h / 36.0,
+                     L.bbox[0], L.bbox[2], L.bbox[1], L.bbox[3]);
+  const int ncut = L.cut_off[4];
+  if (ncut > 0)
+    hipLaunchKernelGGL(k_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->cut_rows, x,
+                       (const double*)nullptr, y, N);
+}
+
+void launch_gt_apply(mgfem_ctx* c, const double* x, double* y) {
+  const Level& L = c->lv[0];
+  launch_zero(c, y, L.n);
+  const int ncut = L.cut_off[4];
+  if (ncut > 0)
+    hipLaunchKernelGGL(k_cut_rows_gt, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, L.cutpos,
+                       c->cut_rows, x, y, c->N);
 }
 
 void launch_mask_inactive(mgfem_ctx* c, double* u) {
@@ -346,21 +482,21 @@ void launch_residual_norm(mgfem_ctx* c, const double* F, const double* u, double
   Level& L = c->lv[0];
   LevelView<double> v{L.A, L.flags, const_cast<double*>(u), nullptr, nullptr, L.N, L.stride, L.n};
   const int ni = L.bbox[1] - L.bbox[0] + 1, nj = L.bbox[3] - L.bbox[2] + 1;
-  const int64_t tot = (int64_t)ni * nj;
-  const int nb = (int)std::min<int64_t>(kRedBlocks, (tot + 255) / 256);
-  hipLaunchKernelGGL(k_resnorm_partial, dim3(nb), dim3(256), 0, c->s, v, F, r_out, L.bbox[0],
+  const dim3 grid((unsigned)std::max(1, (ni + 255) / 256), (unsigned)std::max(1, (nj + 3) / 4));
+  const int nb = (int)(grid.x * grid.y);
+  hipLaunchKernelGGL(k_resnorm_partial, grid, dim3(256), 0, c->s, v, F, r_out, L.bbox[0],
                      L.bbox[2], ni, nj, c->red_partial);
   c->red_seq += 1.0;
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
                      c->red_seq_dev);
 }
 
 void launch_dot_reduce(mgfem_ctx* c, const double* a, const double* b) {
   const int64_t n = c->lv[0].n;
-  const int nb = (int)std::min<int64_t>(kRedBlocks, (n + 255) / 256);
+  const int nb = (int)std::min<int64_t>(kDotBlocks, (n + 255) / 256);  // grid-stride beyond
   hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, c->s, a, b, n, c->red_partial);
   c->red_seq += 1.0;
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
                      c->red_seq_dev);
 }
 

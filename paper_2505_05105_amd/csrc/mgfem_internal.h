@@ -201,6 +201,7 @@ struct mgfem_ctx {
   double* cell_lambda = nullptr;
   double* M = nullptr;
   double* G = nullptr;
+  double* cut_rows = nullptr;  // 18 per cut-cell vertex (M row, G row), in cut-list order
   double* F = nullptr;
   double* F64tmp = nullptr;  // outer residual / scratch on level 0
   double* zero = nullptr;    // all-zero vector of level 0
@@ -212,7 +213,7 @@ struct mgfem_ctx {
   mgfem::CoarsePlan cplan;
   int tile_cfg = 0;            // sweep tile shape selection for large levels
   // reductions
-  double* red_partial = nullptr;  // 2 * kRedBlocks
+  double* red_partial = nullptr;  // one (max, sum) pair per block of the level-0 box kernels
   double* red_out = nullptr;      // 2 doubles on device
   double* red_host = nullptr;     // pinned: max, sum of squares, sequence number
   double red_seq = 0.0;           // sequence number of the last reduction launched
@@ -239,7 +240,14 @@ struct mgfem_ctx {
 
 namespace mgfem {
 
-constexpr int kRedBlocks = 1024;
+
+constexpr int kDotBlocks = 4096;  // blocks of the grid-stride dot product
+// (max, sum) pairs of the reduction buffer: the 2D box kernels of level 0
+// (256 x 4 nodes per block) or the dot product, whichever needs more
+inline int64_t red_pairs(int N) {
+  const int64_t box = (int64_t)((N + 256) / 256) * ((N + 4) / 4);
+  return (box > kDotBlocks ? box : kDotBlocks) + 2;
+}
 
 void set_setup_error(const std::string& msg);  // text returned by mgfem_last_error(NULL)
 
@@ -260,7 +268,10 @@ void launch_rhs(mgfem_ctx* c, const double* f, const double* g, double* F);
 // mixed outer step: u_out = u + e, r = F - A u_out, r32 = float(r), z32 = 0 on
 // the active nodes, and the norm of r as the next reduction (F = lv[0].b)
 void launch_outer(mgfem_ctx* c, const double* u, const float* e, double* u_out, float* r32, float* z32);
-void launch_stencil_apply(mgfem_ctx* c, const double* planes, const double* x, double* y, bool transpose);
+// y = M x and y = G^T x on the fine grid (every node of y written)
+void launch_mass_apply(mgfem_ctx* c, const double* x, double* y);
+void launch_gt_apply(mgfem_ctx* c, const double* x, double* y);
+int build_cut_rows(mgfem_ctx* c);  // gathered M and G rows of the cut-cell vertices
 void launch_mask_inactive(mgfem_ctx* c, double* u);
 void launch_residual_norm(mgfem_ctx* c, const double* F, const double* u, double* r_out);
 void launch_dot_reduce(mgfem_ctx* c, const double* a, const double* b);
