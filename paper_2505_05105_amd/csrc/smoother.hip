@@ -393,10 +393,36 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
     vals[cl_cnt + t] = v;
   }
   __syncthreads();
+  // this thread's first node of every colour, with its row, kept in registers
+  // across the 4 eta phases (a phase then only reads neighbour values)
+  int rt[4];
+  Refs8 rrf[4];
+  T rb[4], rinv[4], rcf[4][8];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int t = gi[4 + c] + threadIdx.x;
+    rt[c] = t < gi[5 + c] ? t : -1;
+    const int tt = rt[c] >= 0 ? t : 0;
+    rrf[c] = srefs[tt];
+    rb[c] = sb[tt];
+    rinv[c] = sinv[tt];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rcf[c][e] = scoef[8 * tt + e];
+  }
   for (int sweep = 0; sweep < a.eta; ++sweep) {
+#pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int c = a.reverse ? 3 - p : p;
-      const int lo = gi[4 + c], hi = gi[5 + c];
+      if (rt[c] >= 0) {
+        T nb[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) nb[e] = vals[rrf[c].r[e]];
+        T acc = rb[c];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc -= rcf[c][e] * nb[e];
+        vals[rt[c]] = acc * rinv[c];
+      }
+      const int lo = gi[4 + c] + blockDim.x, hi = gi[5 + c];
       for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
         const Refs8 rr = srefs[t];
         T nb[8];
