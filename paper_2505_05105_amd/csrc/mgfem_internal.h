@@ -159,6 +159,10 @@ struct CoarsePlan {
   int16_t* cutl = nullptr;
   int16_t* actl = nullptr;  // active nodes per level and colour, as LDS-box indices
   double* inv = nullptr;  // inverse of the coarsest active block (float64)
+  // the LDS content of the coarse part as a prebuilt image (zero vectors, the
+  // lists, slots and rows, the coarsest inverse), float64 and float32 layouts
+  unsigned char* img64 = nullptr;
+  unsigned char* img32 = nullptr;
   int ndesc = 0;
   int lds64 = 0, lds32 = 0;
 };

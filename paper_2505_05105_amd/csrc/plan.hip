@@ -380,7 +380,36 @@ int build_plans(mgfem_ctx* c) {
     if (pass == 0) P.lds64 = off;
     else P.lds32 = off;
   }
+  // LDS images: static parts at their offsets, vectors zero, the inverse
+  // copied in on the device below
+  std::vector<unsigned char> img[2];
+  img[0].assign(P.lds64, 0);
+  img[1].assign(P.lds32, 0);
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = 0; q < P.ndesc; ++q) {
+      const LevHost& h = hosts[q];
+      const int* d = desc.data() + kDesc * (pass * P.ndesc + q);
+      unsigned char* b = img[pass].data();
+      std::memcpy(b + d[15], h.actl.data(), h.actl.size() * 2);
+      std::memcpy(b + d[16], h.slot.data(), h.slot.size() * 2);
+      std::memcpy(b + d[18], h.cutl.data(), h.cutl.size() * 2);
+      if (pass == 0) {
+        std::memcpy(b + d[17], h.coef.data(), h.coef.size() * 8);
+      } else {
+        std::vector<float> f32(h.coef.begin(), h.coef.end());
+        std::memcpy(b + d[17], f32.data(), f32.size() * 4);
+      }
+    }
+  }
   int rc;
+  if ((rc = upload(c, &P.img64, img[0]))) return rc;
+  if ((rc = upload(c, &P.img32, img[1]))) return rc;
+  {
+    const int last64 = desc[kDesc * (P.ndesc - 1) + 20], last32 = desc[kDesc * (2 * P.ndesc - 1) + 20];
+    const size_t ib = (size_t)c->coarse_n * c->coarse_n * sizeof(double);
+    MGFEM_HIP_TRY(hipMemcpyAsync(P.img64 + last64, P.inv, ib, hipMemcpyDeviceToDevice, c->s));
+    MGFEM_HIP_TRY(hipMemcpyAsync(P.img32 + last32, P.inv, ib, hipMemcpyDeviceToDevice, c->s));
+  }
   if ((rc = upload(c, &P.desc, desc))) return rc;
   if ((rc = upload(c, &P.coef, coef))) return rc;
   if (mixed) {

@@ -610,6 +610,8 @@ struct CoarseArgs {
   const int16_t* actl;
   const double* inv;    // inverse of the coarsest active block
   const int16_t* cidx;  // coarsest active nodes as box indices
+  const unsigned char* img;  // prebuilt LDS content of all coarse levels
+  int img_bytes;
   int cn;
   int nlev;
   const T* b_top;
@@ -872,34 +874,47 @@ __device__ void wg_cycle(const CoarseArgs<T>& a, const int* sdesc, unsigned char
 template <class T>
 __device__ void coarse_body(const CoarseArgs<T>& a, unsigned char* base, int* sdesc) {
   for (int q = threadIdx.x; q < kDesc * a.nlev; q += blockDim.x) sdesc[q] = a.desc[q];
-  for (int l = 0; l < a.nlev; ++l) {
-    const int* d = a.desc + kDesc * l;
-    const int W = d[1], H = d[2], nb = W * H;
-    T* x = reinterpret_cast<T*>(base + d[12]);
-    T* b = reinterpret_cast<T*>(base + d[13]);
-    T* r = reinterpret_cast<T*>(base + d[14]);
-    int16_t* sl = reinterpret_cast<int16_t*>(base + d[16]);
-    T* cf = reinterpret_cast<T*>(base + d[17]);
-    int16_t* cl = reinterpret_cast<int16_t*>(base + d[18]);
-    int16_t* act = reinterpret_cast<int16_t*>(base + d[15]);
-    for (int q = threadIdx.x; q < nb; q += blockDim.x) {
-      const int16_t s = a.slot[d[6] + q];
-      x[q] = T(0);
-      r[q] = T(0);
-      sl[q] = s;
-      T bv = T(0);
-      if (l == 0 && s != -2) {
-        const int gi = d[3] + q % W, gj = d[4] + q / W;
-        bv = a.b_top[gi + (int64_t)gj * a.s_top];
+  // the static LDS content of every coarse level (zero vectors, lists, slots,
+  // rows, the coarsest inverse) is one prebuilt image: 16-byte loads, eight
+  // in flight per thread
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(a.img);
+    uint4* dst = reinterpret_cast<uint4*>(base);
+    const int nw = a.img_bytes >> 4;
+    for (int q0 = 0; q0 < nw; q0 += 8 * (int)blockDim.x) {
+      uint4 r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + (int)threadIdx.x + u * (int)blockDim.x;
+        if (q < nw) r[u] = src[q];
       }
-      b[q] = bv;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = q0 + (int)threadIdx.x + u * (int)blockDim.x;
+        if (q < nw) dst[q] = r[u];
+      }
     }
-    for (int q = threadIdx.x; q < 10 * d[19]; q += blockDim.x) cf[q] = a.coef[10 * (int64_t)d[5] + q];
-    for (int q = threadIdx.x; q < d[11] - d[7]; q += blockDim.x) cl[q] = a.cutl[d[7] + q];
-    for (int q = threadIdx.x; q < d[25] - d[21]; q += blockDim.x) act[q] = a.actl[d[21] + q];
-    if (l == a.nlev - 1) {
-      double* inv = reinterpret_cast<double*>(base + d[20]);
-      for (int q = threadIdx.x; q < a.cn * a.cn; q += blockDim.x) inv[q] = a.inv[q];
+  }
+  __syncthreads();
+  // right-hand side of the first coarse level at its active nodes
+  {
+    const WgLev<T> L = wg_level<T>(sdesc, base);
+    const int na = L.act_off[4];
+    for (int t0 = 0; t0 < na; t0 += 8 * (int)blockDim.x) {
+      T v[8];
+      int qq[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + (int)threadIdx.x + u * (int)blockDim.x;
+        qq[u] = t < na ? L.act[t] : -1;
+        if (qq[u] >= 0) {
+          const int gi = L.ox + qq[u] % L.W, gj = L.oy + qq[u] / L.W;
+          v[u] = a.b_top[gi + (int64_t)gj * a.s_top];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (qq[u] >= 0) L.b[qq[u]] = v[u];
     }
   }
   __syncthreads();
@@ -1121,6 +1136,8 @@ void coarse_wg(mgfem_ctx* c, bool reverse) {
   a.actl = P.actl;
   a.inv = P.inv;
   a.cidx = nullptr;
+  a.img = f32 ? P.img32 : P.img64;
+  a.img_bytes = f32 ? P.lds32 : P.lds64;
   a.cn = c->coarse_n;
   a.nlev = P.ndesc;
   a.b_top = Bp<T>(Lc);
@@ -1693,6 +1710,8 @@ void build_batch_layout(std::vector<mgfem_ctx*>& members, std::vector<unsigned c
     A.actl = CP.actl;
     A.inv = CP.inv;
     A.cidx = nullptr;
+    A.img = CP.img32;
+    A.img_bytes = CP.lds32;
     A.cn = c->coarse_n;
     A.nlev = CP.ndesc;
     A.b_top = c->lv[lc].b32;
