@@ -302,12 +302,13 @@ void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32);
 void gather_snap(mgfem_ctx* c, int l, bool fp32);
 int build_plans(mgfem_ctx* c);  // cut groups and the coarse single-workgroup layout
 int build_tile_lists(mgfem_ctx* c);
-// sweep tile shapes: 64 x 64 (512 threads) on the finest level when it is
-// large, 64 x 32 on levels with N >= 1024, 32 x 16 below
+// sweep tile shapes: 64 x 64 (512 threads) on a large finest level of a
+// float64 solver (64 x 32 for the float sweeps of a mixed-precision one), 64 x 32
+// on levels with N >= 1024, 32 x 16 below
 constexpr int kShapeFinest = 0, kShapeLarge = 1, kShapeSmall = 2;
 inline int sweep_shape(const mgfem_ctx* c, int l) {
   const int N = c->lv[l].N;
-  if (l == 0 && N >= 2048) return kShapeFinest;
+  if (l == 0 && N >= 2048) return c->p.precision == MGFEM_PREC_MIXED ? kShapeLarge : kShapeFinest;
   return N >= 1024 ? kShapeLarge : kShapeSmall;
 }
 void set_kernel_attributes();
