@@ -56,7 +56,7 @@ __device__ inline T row_times_x(const LevelView<T>& v, int i, int j, int64_t k, 
   diag = T(8) / T(3);
   const T nb = (x[k - v.s - 1] + x[k - v.s] + x[k - v.s + 1]) + (x[k - 1] + x[k + 1]) +
                (x[k + v.s - 1] + x[k + v.s] + x[k + v.s + 1]);
-  return diag * x[k] - nb / T(3);
+  return diag * x[k] - nb * T(1.0 / 3.0);
 }
 
 // per-block (max |v|, sum v^2) of a block of 256 threads into part[2 b],
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_resnorm_partial(LevelView<double> v, co
     if (!(f & kFlagActive)) continue;
     const int q = threadIdx.x + 1 + (rep + 1) * kSW;
     const double ax = (f & kFlagStored) ? box_row(v.A, v.n, k, sv, q)
-                                        : 8.0 / 3.0 * sv[q] - box_neighbours(sv, q) / 3.0;
+                                        : 8.0 / 3.0 * sv[q] - box_neighbours(sv, q) * (1.0 / 3.0);
     const double r = F[k] - ax;
     if (r_out) r_out[k] = r;
     mx = nanmax(mx, fabs(r));
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void k_outer(LevelView<double> v, const double
     const int q = threadIdx.x + 1 + (rep + 1) * kSW;
     const double uk = sv[q];
     const double ax = (f & kFlagStored) ? box_row(v.A, v.n, k, sv, q)
-                                        : 8.0 / 3.0 * uk - box_neighbours(sv, q) / 3.0;
+                                        : 8.0 / 3.0 * uk - box_neighbours(sv, q) * (1.0 / 3.0);
     const double r = F[k] - ax;
     if (u_out) u_out[k] = uk;
     r32[k] = (float)r;

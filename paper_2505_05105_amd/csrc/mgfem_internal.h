@@ -163,6 +163,7 @@ struct CoarsePlan {
   // lists, slots and rows, the coarsest inverse), float64 and float32 layouts
   unsigned char* img64 = nullptr;
   unsigned char* img32 = nullptr;
+  int static64 = 0, static32 = 0;  // bytes of the static block (the image), whole 1 KB chunks
   int ndesc = 0;
   int lds64 = 0, lds32 = 0;
 };

@@ -332,11 +332,16 @@ int build_plans(mgfem_ctx* c) {
   std::vector<int16_t> slot, cutl, actl;
   for (int pass = 0; pass < 2; ++pass) {
     const int ts = pass == 0 ? 8 : 4;
+    // LDS: first the static block of every level (colour lists, row slots,
+    // rows, cut lists, the coarsest inverse), padded to whole 1 KB chunks
+    // (copied from the image), then the vectors x, b, r of every level
+    // (zeroed in place)
     int off = 0, coef_off = 0, slot_off = 0, cut_off = 0, act_off = 0;
+    std::vector<int> lev_desc(kDesc * P.ndesc, 0);
     for (int q = 0; q < P.ndesc; ++q) {
       const LevHost& h = hosts[q];
       const int nb = h.W * h.H;
-      int d[kDesc] = {0};
+      int* d = lev_desc.data() + kDesc * q;
       d[0] = c->lv[lc + q].N;
       d[1] = h.W;
       d[2] = h.H;
@@ -345,12 +350,6 @@ int build_plans(mgfem_ctx* c) {
       d[5] = coef_off;
       d[6] = slot_off;
       for (int cc = 0; cc < 5; ++cc) d[7 + cc] = cut_off + h.cut_off[cc];
-      d[12] = off;
-      off += align16(nb * ts);
-      d[13] = off;
-      off += align16(nb * ts);
-      d[14] = off;
-      off += align16(nb * ts);
       d[15] = off;
       off += align16(h.nact * 2);
       d[16] = off;
@@ -365,7 +364,6 @@ int build_plans(mgfem_ctx* c) {
         off += align16(c->coarse_n * c->coarse_n * 8);
       }
       for (int cc = 0; cc < 5; ++cc) d[21 + cc] = act_off + h.act_off[cc];
-      desc.insert(desc.end(), d, d + kDesc);
       coef_off += h.nstored;
       slot_off += nb;
       cut_off += h.ncut;
@@ -377,14 +375,29 @@ int build_plans(mgfem_ctx* c) {
         actl.insert(actl.end(), h.actl.begin(), h.actl.end());
       }
     }
+    off = (off + 1023) / 1024 * 1024;
+    if (pass == 0) P.static64 = off;
+    else P.static32 = off;
+    for (int q = 0; q < P.ndesc; ++q) {
+      const LevHost& h = hosts[q];
+      const int nb = h.W * h.H;
+      int* d = lev_desc.data() + kDesc * q;
+      d[12] = off;
+      off += align16(nb * ts);
+      d[13] = off;
+      off += align16(nb * ts);
+      d[14] = off;
+      off += align16(nb * ts);
+    }
+    desc.insert(desc.end(), lev_desc.begin(), lev_desc.end());
     if (pass == 0) P.lds64 = off;
     else P.lds32 = off;
   }
   // LDS images: static parts at their offsets, vectors zero, the inverse
   // copied in on the device below
   std::vector<unsigned char> img[2];
-  img[0].assign(P.lds64, 0);
-  img[1].assign(P.lds32, 0);
+  img[0].assign(P.static64, 0);
+  img[1].assign(P.static32, 0);
   for (int pass = 0; pass < 2; ++pass) {
     for (int q = 0; q < P.ndesc; ++q) {
       const LevHost& h = hosts[q];

@@ -68,6 +68,7 @@ struct SweepArgs {
   const int* tc_off;
   const int* tc_idx;
   const int* tc_pos;
+  const T* zero;  // at least 8 zero bytes: the source of staged nodes off the grid
 };
 
 __device__ inline double nanmax2(double a, double b) { return (b > a || b != b) ? b : a; }
@@ -167,7 +168,13 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   constexpr int PR = 255;  // stored rows of a tile kept in LDS (slot 255: read A)
   constexpr int NCF = (9 * PR + BS - 1) / BS, NRI = (PR + BS - 1) / BS;
   constexpr int KC = 2;                             // core cut vertices prefetched per thread
-  __shared__ T su[RH * RW];
+  constexpr int ES = (int)sizeof(T) / 4;            // dwords per value
+  constexpr int NDW = RW * RH * ES, NCH = (NDW + 63) / 64;
+  __shared__ __align__(16) T su[NCH * 64 / ES];  // the region, rounded up to whole 64-dword chunks
+  // coarse tile under the region (fused prolongation): parents of the region's nodes
+  constexpr int CW = RW / 2 + 2, CH = RH / 2 + 2;
+  constexpr int NCDW = CW * CH * ES, NCCH = (NCDW + 63) / 64;
+  __shared__ __align__(16) T sxc[NCCH * 64 / ES];
   __shared__ T scf[9 * PR];
   __shared__ uint8_t sslot[RH * RW];  // stored node: its row in scf (255: read A); others unused
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
@@ -220,36 +227,42 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
     cix[u] = e < ncut ? a.tc_idx[c0 + e] : -1;
     cpo[u] = e < ncut ? a.tc_pos[c0 + e] : 0;
   }
-  T ru[NU];
-#pragma unroll
-  for (int it = 0; it < NU; ++it) {
-    const int q = tid + BS * it;
-    const int gi = ox + q % RW, gj = oy + q / RW;
-    const bool in = q < RW * RH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N;
-    T v = in ? a.xin[gi + (int64_t)gj * a.s] : T(0);
-    if (in && a.xc) {
-      // + P x_c: bilinear interpolation from the (up to) four coarse parents,
-      // written without branches: for an even index both parents coincide
-      const int I0 = gi >> 1, I1 = (gi + 1) >> 1, J0 = gj >> 1, J1 = (gj + 1) >> 1;
-      const int64_t r0 = (int64_t)J0 * a.sc, r1 = (int64_t)J1 * a.sc;
-      v += T(0.25) * ((a.xc[I0 + r0] + a.xc[I1 + r0]) + (a.xc[I0 + r1] + a.xc[I1 + r1]));
+  // the staged iterate goes straight from global memory into LDS (one dword
+  // per lane, 64-dword chunks per wave instruction, no registers)
+  {
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int ch = wave; ch < NCH; ch += BS / 64) {
+      const int dw = ch * 64 + lane;
+      const int e = dw / ES;
+      const int gi = ox + e % RW, gj = oy + e / RW;
+      const bool in = dw < NDW && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N;
+      const char* src = reinterpret_cast<const char*>(in ? a.xin + gi + (int64_t)gj * a.s : a.zero) + 4 * (dw % ES);
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(su) + ch * 256),
+                                       4, 0, 0);
     }
-    ru[it] = v;
+  }
+  // the coarse iterate under the region, the same way (fused prolongation)
+  const int cox = ox >> 1, coy = oy >> 1;  // floor: the parents of the region's first node
+  if (a.xc) {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int Nc = a.N >> 1;
+    for (int ch = wave; ch < NCCH; ch += BS / 64) {
+      const int dw = ch * 64 + lane;
+      const int e = dw / ES;
+      const int I = cox + e % CW, J = coy + e / CW;
+      const bool in = dw < NCDW && I >= 0 && J >= 0 && I <= Nc && J <= Nc;
+      const char* src = reinterpret_cast<const char*>(in ? a.xc + I + (int64_t)J * a.sc : a.zero) + 4 * (dw % ES);
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(sxc) + ch * 256),
+                                       4, 0, 0);
+    }
   }
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int it = 0; it < NP; ++it) {
       const int q = pq[p][it];
-      T bv = T(0);
-      if (q >= 0 && (pf[p][it] & kFlagActive)) bv = a.b[(ox + q % RW) + (int64_t)(oy + q / RW) * a.s];
-      pb[p][it] = bv;
+      pb[p][it] = q >= 0 ? a.b[(ox + q % RW) + (int64_t)(oy + q / RW) * a.s] : T(0);
     }
-#pragma unroll
-  for (int it = 0; it < NU; ++it) {
-    const int q = tid + BS * it;
-    if (q < RW * RH) su[q] = ru[it];
-  }
 #pragma unroll
   for (int u = 0; u < NCF; ++u) {
     const int q = tid + u * BS;
@@ -259,7 +272,23 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   for (int u = 0; u < NRI; ++u)
     if (rix[u] >= 0) sslot[rix[u]] = (uint8_t)(tid + u * BS);
   for (int e = PR + tid; e < nrow; e += BS) sslot[a.tp_idx[p0 + e]] = (uint8_t)PR;  // beyond the LDS rows
+  __builtin_amdgcn_s_waitcnt(0);  // the global->LDS loads of this thread have landed
   __syncthreads();
+  if (a.xc) {
+    // + P x_c: bilinear interpolation from the (up to) four coarse parents,
+    // written without branches (for an even index both parents coincide)
+#pragma unroll
+    for (int it = 0; it < NU; ++it) {
+      const int q = tid + BS * it;
+      const int gi = ox + q % RW, gj = oy + q / RW;
+      if (q < RW * RH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) {
+        const int I0 = (gi >> 1) - cox, I1 = ((gi + 1) >> 1) - cox;
+        const int J0 = ((gj >> 1) - coy) * CW, J1 = (((gj + 1) >> 1) - coy) * CW;
+        su[q] += T(0.25) * ((sxc[I0 + J0] + sxc[I1 + J0]) + (sxc[I0 + J1] + sxc[I1 + J1]));
+      }
+    }
+    __syncthreads();
+  }
   auto in_core = [&](int q) {
     const int ri = q % RW, rj = q / RW;
     return ri >= kHalo && ri < kHalo + TW && rj >= kHalo && rj < kHalo + TH && ox + ri <= a.i1 && oy + rj <= a.j1;
@@ -283,7 +312,7 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
             ax = a.A[4 * a.n + k] * su[q] + stored_offdiag<T, RW>(a.A, a.n, k, su, q);
           }
         } else {
-          ax = T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) / T(3);
+          ax = T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) * T(1.0 / 3.0);
         }
         const double r = (double)(pb[p][it] - ax);
         mx = nanmax2(mx, fabs(r));
@@ -482,7 +511,7 @@ struct ResArgs {
 template <class T, int RW>
 __device__ inline T row_product(const T* __restrict__ A, int64_t n, int64_t k, bool stored, const T* su, int q) {
   if (stored) return A[4 * n + k] * su[q] + stored_offdiag<T, RW>(A, n, k, su, q);
-  return T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) / T(3);
+  return T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) * T(1.0 / 3.0);
 }
 
 template <class T, int CW, int CH>
@@ -610,8 +639,9 @@ struct CoarseArgs {
   const int16_t* actl;
   const double* inv;    // inverse of the coarsest active block
   const int16_t* cidx;  // coarsest active nodes as box indices
-  const unsigned char* img;  // prebuilt LDS content of all coarse levels
-  int img_bytes;
+  const unsigned char* img;  // prebuilt static LDS block of all coarse levels
+  int img_bytes;             // its size (whole 1 KB chunks)
+  int lds_bytes;             // the whole LDS block (the vectors follow the image)
   int cn;
   int nlev;
   const T* b_top;
@@ -688,7 +718,7 @@ __device__ inline T lds_res(const WgLev<T>& L, int q) {
   }
   const T nb = (x[q - W - 1] + x[q - W] + x[q - W + 1]) + (x[q - 1] + x[q + 1]) +
                (x[q + W - 1] + x[q + W] + x[q + W + 1]);
-  return bv - (T(8) / T(3) * x[q] - nb / T(3));
+  return bv - (T(8) / T(3) * x[q] - nb * T(1.0 / 3.0));
 }
 
 // Gauss-Seidel value at q from a row slot and right-hand side held in registers
@@ -874,26 +904,18 @@ __device__ void wg_cycle(const CoarseArgs<T>& a, const int* sdesc, unsigned char
 template <class T>
 __device__ void coarse_body(const CoarseArgs<T>& a, unsigned char* base, int* sdesc) {
   for (int q = threadIdx.x; q < kDesc * a.nlev; q += blockDim.x) sdesc[q] = a.desc[q];
-  // the static LDS content of every coarse level (zero vectors, lists, slots,
-  // rows, the coarsest inverse) is one prebuilt image: 16-byte loads, eight
-  // in flight per thread
+  // the static LDS block of every coarse level (lists, slots, rows, the
+  // coarsest inverse) comes from a prebuilt image with global->LDS loads of
+  // 16 bytes per lane, all in flight together; the vectors are zeroed
   {
-    const uint4* src = reinterpret_cast<const uint4*>(a.img);
-    uint4* dst = reinterpret_cast<uint4*>(base);
-    const int nw = a.img_bytes >> 4;
-    for (int q0 = 0; q0 < nw; q0 += 8 * (int)blockDim.x) {
-      uint4 r[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = q0 + (int)threadIdx.x + u * (int)blockDim.x;
-        if (q < nw) r[u] = src[q];
-      }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int q = q0 + (int)threadIdx.x + u * (int)blockDim.x;
-        if (q < nw) dst[q] = r[u];
-      }
-    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int ch = wave; ch < (a.img_bytes >> 10); ch += nw)
+      __builtin_amdgcn_global_load_lds(a.img + ch * 1024 + lane * 16,
+                                       (__attribute__((address_space(3))) void*)(base + ch * 1024), 16, 0, 0);
+    uint4* vz = reinterpret_cast<uint4*>(base + a.img_bytes);
+    const uint4 z = {0u, 0u, 0u, 0u};
+    for (int q = threadIdx.x; q < ((a.lds_bytes - a.img_bytes) >> 4); q += blockDim.x) vz[q] = z;
+    __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
   // right-hand side of the first coarse level at its active nodes
@@ -1006,6 +1028,7 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   a.tc_off = L.tc_off;
   a.tc_idx = L.tc_idx;
   a.tc_pos = L.tc_pos;
+  a.zero = reinterpret_cast<const T*>(c->zero);
   if (c->prof.on && std::is_same<T, double>::value && l == 0) {
     // algorithmic bytes: per active row x read and written, b read, its flag,
     // the 72 bytes of a stored row; a fused prolongation also reads x_c
@@ -1137,7 +1160,8 @@ void coarse_wg(mgfem_ctx* c, bool reverse) {
   a.inv = P.inv;
   a.cidx = nullptr;
   a.img = f32 ? P.img32 : P.img64;
-  a.img_bytes = f32 ? P.lds32 : P.lds64;
+  a.img_bytes = f32 ? P.static32 : P.static64;
+  a.lds_bytes = f32 ? P.lds32 : P.lds64;
   a.cn = c->coarse_n;
   a.nlev = P.ndesc;
   a.b_top = Bp<T>(Lc);
@@ -1418,7 +1442,7 @@ __device__ inline T glob_row(const T* __restrict__ A, int64_t n, const T* x, int
   } else {  // interior Q1 row: every neighbour exists
     diag = T(8) / T(3);
     off = -((x[k - s - 1] + x[k - s] + x[k - s + 1]) + (x[k - 1] + x[k + 1]) +
-            (x[k + s - 1] + x[k + s] + x[k + s + 1])) / T(3);
+            (x[k + s - 1] + x[k + s] + x[k + s + 1])) * T(1.0 / 3.0);
   }
   return diag * x[k] + off;
 }
@@ -1711,7 +1735,8 @@ void build_batch_layout(std::vector<mgfem_ctx*>& members, std::vector<unsigned c
     A.inv = CP.inv;
     A.cidx = nullptr;
     A.img = CP.img32;
-    A.img_bytes = CP.lds32;
+    A.img_bytes = CP.static32;
+    A.lds_bytes = CP.lds32;
     A.cn = c->coarse_n;
     A.nlev = CP.ndesc;
     A.b_top = c->lv[lc].b32;

@@ -118,7 +118,9 @@ def test_converged_solution_at_n4096(name):
     ug = u.cpu().numpy()
     assert rel_max(ug, ref.u) < 1e-10
     assert np.abs(hist[1:] / hist[:-1] - ref.rho).max() < 0.02
-    np.testing.assert_allclose(hist, ref.hist, rtol=1e-8)
+    # each norm is of a residual F - A u whose rounding is of size
+    # (stencil size) eps ||F||, whatever the residual's own size
+    np.testing.assert_allclose(hist, ref.hist, rtol=1e-8, atol=50 * 2.2e-16 * hist[0])
     assert hist[-1] <= 1e-10 * np.abs(F).max()
     assert np.all(ug[~d.active] == 0)
 
