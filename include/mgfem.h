@@ -70,7 +70,15 @@ enum mgfem_precision {
                            float64 outer residual, geometry and coarsest solve */
 };
 
-enum mgfem_cycle { MGFEM_CYCLE_V = 1, MGFEM_CYCLE_W = 2 }; /* gamma* of section 3.2 */
+enum mgfem_cycle {
+  MGFEM_CYCLE_V = 1,        /* gamma* = 1 (section 3.2) */
+  MGFEM_CYCLE_W = 2,        /* gamma* = 2 (section 3.2) */
+  MGFEM_CYCLE_TWO_GRID = 3  /* two-grid correction scheme (Algorithm 1 of section 3.1):
+                               the first coarse problem is solved by coarse_cycles
+                               V-cycles from zero, which reduce its error far below
+                               float64 rounding (an exact solve in effect); the
+                               levels below serve that inner solve only */
+};
 
 #define MGFEM_SOLVE_WARM_START 1u /* start from the u passed in, not from 0 */
 
@@ -85,6 +93,7 @@ typedef struct {
   int32_t precision;    /* enum mgfem_precision, default MGFEM_PREC_FP64 */
   int32_t cycle;        /* enum mgfem_cycle, default MGFEM_CYCLE_V */
   double x_lo, y_lo, x_hi, y_hi; /* square box; default [-1, 1]^2 */
+  int32_t coarse_cycles; /* MGFEM_CYCLE_TWO_GRID: V-cycles of the coarse solve (1..1000); default 40 */
 } mgfem_params;
 
 typedef struct {

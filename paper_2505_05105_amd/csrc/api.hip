@@ -34,7 +34,10 @@ int check_params(const mgfem_params& p, int N, std::string& why) {
     return why = "nu1/nu2/eta", 1;
   if (p.coarsest_n < 1 || p.coarsest_n > 16) return why = "coarsest_n must be in [1, 16]", 1;
   if (p.precision != MGFEM_PREC_FP64 && p.precision != MGFEM_PREC_MIXED) return why = "precision", 1;
-  if (p.cycle != MGFEM_CYCLE_V && p.cycle != MGFEM_CYCLE_W) return why = "cycle", 1;
+  if (p.cycle != MGFEM_CYCLE_V && p.cycle != MGFEM_CYCLE_W && p.cycle != MGFEM_CYCLE_TWO_GRID)
+    return why = "cycle", 1;
+  if (p.cycle == MGFEM_CYCLE_TWO_GRID && (p.coarse_cycles < 1 || p.coarse_cycles > 1000))
+    return why = "coarse_cycles must be 1..1000", 1;
   const double wx = p.x_hi - p.x_lo, wy = p.y_hi - p.y_lo;
   if (!(wx > 0.0) || !(wy > 0.0) || std::fabs(wx - wy) > 1e-12 * wx)
     return why = "the box must be a non-empty square", 1;
@@ -189,6 +192,7 @@ int mgfem_default_params(mgfem_params* p) {
   p->coarsest_n = 4;
   p->precision = MGFEM_PREC_FP64;
   p->cycle = MGFEM_CYCLE_V;
+  p->coarse_cycles = 40;
   p->x_lo = -1.0;
   p->y_lo = -1.0;
   p->x_hi = 1.0;

@@ -648,6 +648,7 @@ struct CoarseArgs {
   T* x_top;
   int s_top;
   int nu1, nu2, eta, reverse, gstar;
+  int reps;  // cycles of the first coarse level from its current iterate
 };
 
 // pointers of one coarse level inside the LDS block
@@ -940,8 +941,8 @@ __device__ void coarse_body(const CoarseArgs<T>& a, unsigned char* base, int* sd
     }
   }
   __syncthreads();
-  // gamma* cycles on the first coarse level, each continuing from the last
-  for (int g = 0; g < a.gstar; ++g) wg_cycle<T>(a, sdesc, base);
+  // reps cycles on the first coarse level, each continuing from the last
+  for (int g = 0; g < a.reps; ++g) wg_cycle<T>(a, sdesc, base);
   const WgLev<T> L = wg_level<T>(sdesc, base);
   for (int t = threadIdx.x; t < L.act_off[4]; t += blockDim.x) {
     const int q = L.act[t];
@@ -1146,7 +1147,7 @@ void prolong(mgfem_ctx* c, int l) {
 }
 
 template <class T>
-void coarse_wg(mgfem_ctx* c, bool reverse) {
+void coarse_wg(mgfem_ctx* c, bool reverse, int reps) {
   CoarsePlan& P = c->cplan;
   Level& Lc = c->lv[P.lc];
   CoarseArgs<T> a;
@@ -1172,6 +1173,7 @@ void coarse_wg(mgfem_ctx* c, bool reverse) {
   a.eta = c->p.eta;
   a.reverse = reverse ? 1 : 0;
   a.gstar = c->p.cycle == MGFEM_CYCLE_W ? 2 : 1;
+  a.reps = reps;
   const int lds = std::is_same<T, double>::value ? P.lds64 : P.lds32;
   hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kCoarseThreads), lds, c->s, a);
   Lc.cur = 0;
@@ -1181,7 +1183,7 @@ template <class T>
 void cycle_level(mgfem_ctx* c, int l, bool reverse, bool first_sweep_done = false) {
   const int nl = (int)c->lv.size();
   if (c->cplan.lc >= 0 && l == c->cplan.lc) {
-    coarse_wg<T>(c, reverse);
+    coarse_wg<T>(c, reverse, 1);
     return;
   }
   if (l == nl - 1) return;  // unreachable: the coarse plan always covers the coarsest level
@@ -1193,10 +1195,13 @@ void cycle_level(mgfem_ctx* c, int l, bool reverse, bool first_sweep_done = fals
   }
   if (c->lv[l].N >= 1024) launch_resrestrict<T, 32, 16>(c, l);
   else launch_resrestrict<T, 16, 8>(c, l);
-  const int gstar = c->p.cycle == MGFEM_CYCLE_W ? 2 : 1;
-  if (l + 1 == c->cplan.lc) coarse_wg<T>(c, reverse);  // runs its gamma* cycles itself
+  // coarse-grid visits: gamma* (section 3.2); the two-grid scheme instead
+  // solves the first coarse problem with coarse_cycles V-cycles from zero
+  const bool two_grid = c->p.cycle == MGFEM_CYCLE_TWO_GRID && l == 0;
+  const int visits = two_grid ? c->p.coarse_cycles : (c->p.cycle == MGFEM_CYCLE_W ? 2 : 1);
+  if (l + 1 == c->cplan.lc) coarse_wg<T>(c, reverse, visits);  // runs its visits itself
   else
-    for (int g = 0; g < gstar; ++g) cycle_level<T>(c, l + 1, reverse);
+    for (int g = 0; g < visits; ++g) cycle_level<T>(c, l + 1, reverse);
   if (reverse || post == 0) {
     prolong<T>(c, l);
     for (int s = 0; s < post; ++s) smooth<T>(c, l, reverse);
@@ -1747,6 +1752,7 @@ void build_batch_layout(std::vector<mgfem_ctx*>& members, std::vector<unsigned c
     A.eta = c->p.eta;
     A.reverse = 0;
     A.gstar = 1;
+    A.reps = 1;
     lds = std::max(lds, CP.lds32);
     std::memcpy(probs_bytes.data() + i * sizeof(BProb), &P, sizeof(BProb));
   }
