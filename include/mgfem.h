@@ -80,6 +80,16 @@ enum mgfem_cycle {
                                levels below serve that inner solve only */
 };
 
+/* coarse-level operators (section 4.3 and section 5) */
+enum mgfem_coarse_op {
+  MGFEM_COARSE_GALERKIN = 0,     /* A_{2h} = R A_h P (eq. galerkin) */
+  MGFEM_COARSE_REDISCRETISED = 1 /* every coarse level assembled from scratch on its own grid:
+                                    psi injected at the coarse nodes (coarse node (I, J) is
+                                    fine node (2I, 2J)), snapped, classified, stabilised and
+                                    assembled with the coarse cell size; its extra-smoothing
+                                    set is the vertices of its own cut cells */
+};
+
 #define MGFEM_SOLVE_WARM_START 1u /* start from the u passed in, not from 0 */
 
 typedef struct {
@@ -94,6 +104,7 @@ typedef struct {
   int32_t cycle;        /* enum mgfem_cycle, default MGFEM_CYCLE_V */
   double x_lo, y_lo, x_hi, y_hi; /* square box; default [-1, 1]^2 */
   int32_t coarse_cycles; /* MGFEM_CYCLE_TWO_GRID: V-cycles of the coarse solve (1..1000); default 40 */
+  int32_t coarse_op;     /* enum mgfem_coarse_op, default MGFEM_COARSE_GALERKIN */
 } mgfem_params;
 
 typedef struct {

@@ -111,12 +111,24 @@ class Hierarchy:
         return x
 
 
-def build_hierarchy(disc, coarsest_n=4, dense_limit=4000) -> Hierarchy:
+def build_hierarchy(disc, coarsest_n=4, dense_limit=4000, rediscretise=None) -> Hierarchy:
     """Galerkin hierarchy A_{l+1} = P^T A_l P down to a grid of coarsest_n
-    cells per side, computed as a generic sparse triple product."""
+    cells per side, computed as a generic sparse triple product.
+
+    rediscretise = (psi, kw) instead assembles every coarse operator from
+    scratch on its own grid (section 4.3 and section 5, the alternative to the
+    Galerkin condition): psi, the unsnapped fine nodal level set, is injected
+    at the coarse nodes (coarse node (I, J) is fine node (2I, 2J)) and
+    assembled with the fine grid's parameters kw (gamma, alpha, rule,
+    lambda_fixed) and the coarse cell size; the extra-smoothing set of a
+    coarse level is then the vertices of its own cut cells."""
     N = disc.N
     if N % coarsest_n or (N // coarsest_n) & (N // coarsest_n - 1):
         raise ValueError("N must be coarsest_n times a power of two")
+    if rediscretise is not None:
+        from . import assembly as asm
+        psi_in, akw = rediscretise
+        psi_in = np.asarray(psi_in, dtype=np.float64).reshape(N + 1, N + 1)
     cell_cut = (disc.cell_type != geo.EXTERNAL) & (disc.cell_type != geo.INTERNAL)
     A = disc.A.tocsr()
     levels = []
@@ -137,9 +149,15 @@ def build_hierarchy(disc, coarsest_n=4, dense_limit=4000) -> Hierarchy:
         levels.append(lv)
         if P is None:
             break
-        A = (P.T @ A @ P).tocsr()
-        A.eliminate_zeros()
-        cell_cut = coarsen_cut_cells(cell_cut, N)
+        if rediscretise is None:
+            A = (P.T @ A @ P).tocsr()
+            A.eliminate_zeros()
+            cell_cut = coarsen_cut_cells(cell_cut, N)
+        else:
+            step = disc.N // (N // 2)
+            dc = asm.assemble(psi_in[::step, ::step].ravel(), N // 2, box=disc.box, **akw)
+            A = dc.A.tocsr()
+            cell_cut = (dc.cell_type != geo.EXTERNAL) & (dc.cell_type != geo.INTERNAL)
         N //= 2
     last = levels[-1]
     idx = np.nonzero(last.active)[0]
@@ -212,7 +230,11 @@ def cycle(hier: Hierarchy, x, b, nu1=2, nu2=1, eta=4, gamma_star=1, level=0,
     Pre-smoothing nu1 steps, residual, restriction R = P^T, gamma_star cycles
     on the next level from a zero guess (an exact solve on the coarsest),
     prolongation and correction, post-smoothing nu2 steps (Algorithm 1 made
-    recursive, section 3.2).  Corrections are only added at active nodes."""
+    recursive, section 3.2).  The unknowns of a level are its active nodes
+    (eq. Vhact): the residual is taken there only, and corrections are only
+    added there.  With Galerkin operators the residual vanishes at inactive
+    nodes anyway; with rediscretised ones an inactive coarse node can receive
+    restricted residual, which is not part of the coarse problem."""
     lv = hier.levels[level]
     if level == hier.L:
         x[:] = hier.coarse_solve(b)
@@ -221,7 +243,7 @@ def cycle(hier: Hierarchy, x, b, nu1=2, nu2=1, eta=4, gamma_star=1, level=0,
         else (lambda xx, bb: lexicographic_step(lv, xx, bb, eta))
     for _ in range(nu1):
         step(x, b)
-    r = b - lv.A @ x
+    r = np.where(lv.active, b - lv.A @ x, 0.0)
     bc = lv.P.T @ r
     xc = np.zeros_like(bc)
     for _ in range(gamma_star):

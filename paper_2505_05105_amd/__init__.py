@@ -15,8 +15,9 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (CYCLE_TWO_GRID, CYCLE_V, CYCLE_W, PREC_FP64, PREC_MIXED, STAB_FIXED, STAB_LOCAL_EIG,  # noqa: F401
-                   STAB_PAPER, MgfemError, default_params)
+from ._lib import (COARSE_GALERKIN, COARSE_REDISCRETISED, CYCLE_TWO_GRID, CYCLE_V, CYCLE_W,  # noqa: F401
+                   PREC_FP64, PREC_MIXED, STAB_FIXED, STAB_LOCAL_EIG, STAB_PAPER, MgfemError,
+                   default_params)
 
 __all__ = ["Solver", "BatchedSolver", "GhostFEMSolve", "MgfemError", "default_params"]
 

@@ -17,6 +17,7 @@ OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_DIVERGED, \
 STAB_PAPER, STAB_LOCAL_EIG, STAB_FIXED = 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
 CYCLE_V, CYCLE_W, CYCLE_TWO_GRID = 1, 2, 3
+COARSE_GALERKIN, COARSE_REDISCRETISED = 0, 1
 SOLVE_WARM_START = 1
 EXPORT_PSI, EXPORT_CELL_TYPE, EXPORT_CELL_LAMBDA, EXPORT_A, EXPORT_M, EXPORT_G, \
     EXPORT_NODE_FLAGS, EXPORT_RHS = range(8)
@@ -35,7 +36,7 @@ class Params(C.Structure):
         ("snap_alpha", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("eta", C.c_int32),
         ("coarsest_n", C.c_int32), ("precision", C.c_int32), ("cycle", C.c_int32),
         ("x_lo", C.c_double), ("y_lo", C.c_double), ("x_hi", C.c_double), ("y_hi", C.c_double),
-        ("coarse_cycles", C.c_int32),
+        ("coarse_cycles", C.c_int32), ("coarse_op", C.c_int32),
     ]
 
 

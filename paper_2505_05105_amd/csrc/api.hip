@@ -38,6 +38,7 @@ int check_params(const mgfem_params& p, int N, std::string& why) {
     return why = "cycle", 1;
   if (p.cycle == MGFEM_CYCLE_TWO_GRID && (p.coarse_cycles < 1 || p.coarse_cycles > 1000))
     return why = "coarse_cycles must be 1..1000", 1;
+  if (p.coarse_op != MGFEM_COARSE_GALERKIN && p.coarse_op != MGFEM_COARSE_REDISCRETISED) return why = "coarse_op", 1;
   const double wx = p.x_hi - p.x_lo, wy = p.y_hi - p.y_lo;
   if (!(wx > 0.0) || !(wy > 0.0) || std::fabs(wx - wy) > 1e-12 * wx)
     return why = "the box must be a non-empty square", 1;
@@ -193,6 +194,7 @@ int mgfem_default_params(mgfem_params* p) {
   p->precision = MGFEM_PREC_FP64;
   p->cycle = MGFEM_CYCLE_V;
   p->coarse_cycles = 40;
+  p->coarse_op = MGFEM_COARSE_GALERKIN;
   p->x_lo = -1.0;
   p->y_lo = -1.0;
   p->x_hi = 1.0;
@@ -291,7 +293,7 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
   }
   rc = setup_geometry(c, psi_dev);
   if (rc != MGFEM_OK) return bail(rc);
-  rc = setup_hierarchy(c);
+  rc = setup_hierarchy(c, psi_dev);
   if (rc != MGFEM_OK) return bail(rc);
   SETUP_TRY(hipEventRecord(e1, c->s));
   Stats st{};

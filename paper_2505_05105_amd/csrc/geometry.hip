@@ -502,8 +502,8 @@ __global__ void k_assemble(const double* __restrict__ psi, int N, mgfem_params p
     }
     for (int q = 0; q < 9; ++q) {
       A[q * n + k] = a[q];
-      Mm[q * n + k] = m[q];
-      G[q * n + k] = g[q];
+      if (Mm) Mm[q * n + k] = m[q];  // mass and boundary load: finest level only
+      if (G) G[q * n + k] = g[q];
     }
     uint8_t f = 0;
     if (active) f |= kFlagActive;
@@ -515,7 +515,51 @@ __global__ void k_assemble(const double* __restrict__ psi, int N, mgfem_params p
   if (threadIdx.x == 0 && nact) atomicAdd(&st->active, (unsigned long long)nact);
 }
 
+// psi of a coarse grid: the fine input at every step-th node in each direction
+__global__ void k_inject(const double* __restrict__ psi_in, int N0, int step, double* __restrict__ out, int Nl) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t nl = (int64_t)(Nl + 1) * (Nl + 1);
+  if (k >= nl) return;
+  const int I = (int)(k % (Nl + 1)), J = (int)(k / (Nl + 1));
+  out[k] = psi_in[(int64_t)I * step + (int64_t)J * step * (N0 + 1)];
+}
+
 }  // namespace
+
+int assemble_level(mgfem_ctx* c, int l, const double* psi_in) {
+  Level& L = c->lv[l];
+  const int N = L.N;
+  const int64_t n = L.n, nc = (int64_t)N * N;
+  const double h = (c->p.x_hi - c->p.x_lo) / N;
+  const int tb = 256;
+  double *raw = nullptr, *psi = nullptr, *lam = nullptr;
+  uint8_t* ct = nullptr;
+  Stats* st = nullptr;  // statistics of the coarse grids are not reported
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &raw, n));
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &psi, n));
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &lam, nc));
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &ct, nc));
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &st, 1));
+  {
+    Stats init{};
+    init.min_theta_bits = 0x7ff0000000000000ull;
+    MGFEM_HIP_TRY(hipMemcpyAsync(st, &init, sizeof(init), hipMemcpyHostToDevice, c->s));
+  }
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &L.A, 9 * n));
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &L.flags, n));
+  MGFEM_HIP_TRY(ctx_alloc_t(c, &L.cellcut, nc));
+  hipLaunchKernelGGL(k_inject, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, psi_in, c->N, c->N / N, raw,
+                     N);
+  hipLaunchKernelGGL(k_snap, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)raw, psi, n,
+                     pow(h, c->p.snap_alpha), st);
+  hipLaunchKernelGGL(k_classify, dim3((unsigned)((nc + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)psi, N,
+                     c->p, h, ct, lam, L.cellcut, st);
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)psi, N,
+                     c->p, h, (const uint8_t*)ct, (const double*)lam, L.A, (double*)nullptr, (double*)nullptr,
+                     L.flags, st);
+  MGFEM_HIP_TRY(hipGetLastError());
+  return MGFEM_OK;
+}
 
 int setup_geometry(mgfem_ctx* c, const double* psi_in) {
   const int N = c->N;

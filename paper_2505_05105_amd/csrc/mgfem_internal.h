@@ -265,7 +265,11 @@ hipError_t ctx_alloc_t(mgfem_ctx* c, T** p, size_t count) {
 
 // setup stages (geometry.hip, hierarchy.hip)
 int setup_geometry(mgfem_ctx* c, const double* psi_in);
-int setup_hierarchy(mgfem_ctx* c);
+int setup_hierarchy(mgfem_ctx* c, const double* psi_in);
+// coarse level l assembled from scratch on its own grid from the fine input
+// level set (injection, snapping, classification, stabilisation, assembly):
+// fills lv[l].A, flags and cellcut (MGFEM_COARSE_REDISCRETISED)
+int assemble_level(mgfem_ctx* c, int l, const double* psi_in);
 
 // solve stages (cycle.hip)
 // F = M f + G g, and its norm (max, sum of squares) as the next reduction

@@ -102,3 +102,46 @@ def test_two_grid_parameter_checks():
         mg.Solver(p.psi, 64, cycle=mg.CYCLE_TWO_GRID, coarse_cycles=0)
     with pytest.raises(mg.MgfemError):
         mg.Solver(p.psi, 64, cycle=4)
+
+
+def _planes(A, N):
+    from helpers import planes_from_csr
+    return planes_from_csr(A, N)
+
+
+@pytest.mark.parametrize("name,N", [("flower", 128), ("ellipse", 64)])
+def test_rediscretised_levels_match_oracle(name, N):
+    """Every coarse operator assembled on its own grid (sections 4.3 and 5):
+    stencils and active sets of every level against the oracle's."""
+    mg = _gpu()
+    p = W.flower_mms(N) if name == "flower" else W.ellipse_mms(N)
+    d = oasm.assemble(p.psi, N)
+    H = omg.build_hierarchy(d, rediscretise=(p.psi, {}))
+    s = mg.Solver(p.psi, N, coarse_op=mg.COARSE_REDISCRETISED)
+    assert s.n_levels == len(H.levels)
+    for lv in range(1, s.n_levels):
+        Nl = s.level_n(lv)
+        got = s.export(mg._lib.EXPORT_A, lv).cpu().numpy().reshape(9, -1)
+        ref = _planes(H.levels[lv].A, Nl)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), lv
+        fl = s.export(mg._lib.EXPORT_NODE_FLAGS, lv).cpu().numpy().astype(int)
+        assert np.array_equal((fl & 1) == 1, H.levels[lv].active), lv
+
+
+def test_rediscretised_cycles_match_oracle():
+    mg = _gpu()
+    N = 128
+    p = W.flower_mms(N)
+    d = oasm.assemble(p.psi, N)
+    H = omg.build_hierarchy(d, rediscretise=(p.psi, {}))
+    F = d.rhs(p.f, p.g)
+    s = mg.Solver(p.psi, N, coarse_op=mg.COARSE_REDISCRETISED)
+    u, hist = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
+    ref = omg.solve(H, F, tol=-1.0, max_cycles=3)
+    assert rel_max(u.cpu().numpy(), ref.u) < 1e-11
+    u, hist = s.solve(p.f, p.g, tol=1e-10, max_cycles=80)
+    ref = omg.solve(H, F, tol=1e-10, max_cycles=80)
+    assert s.last_status == 0 and ref.converged
+    assert len(hist) == len(ref.hist)
+    assert rel_max(u.cpu().numpy(), ref.u) < 1e-10
+    assert np.abs(hist[1:] / hist[:-1] - ref.rho).max() < 0.02
