@@ -9,7 +9,8 @@ u_k = B_k F with F = M f + G g.  Its exact discrete adjoint applies B_k^T,
 which is k cycles of the transposed cycle from a zero guess: every smoothing
 phase in reverse order and the pre/post smoothing counts swapped (the Galerkin
 coarse correction with R = P^T is self-adjoint in the A inner product, and
-A = A^T).  Then dJ/df = M^T lam = M lam and dJ/dg = G^T lam.
+A = A^T).  Then dJ/df = M^T lam = M lam, dJ/dg = G^T lam and, with Neumann
+segments, dJ/dg_N = GN^T lam.
 """
 from __future__ import annotations
 
@@ -35,6 +36,13 @@ def adjoint_solve(hier, dJdu, tol=1e-10, max_cycles=50, nu1=2, nu2=1, eta=4):
 def gradients(disc, lam):
     """(dJ/df, dJ/dg) = (M lam, G^T lam)."""
     return disc.M @ lam, disc.G.T @ lam
+
+
+def neumann_gradient(disc, lam):
+    """dJ/dg_N = GN^T lam (GN symmetric); zero without Neumann segments."""
+    if disc.GN is None:
+        return np.zeros(disc.n)
+    return disc.GN.T @ lam
 
 
 def forward(hier, disc, f, g, cycles, nu1=2, nu2=1, eta=4):

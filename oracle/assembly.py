@@ -19,6 +19,16 @@ through their nodal Q1 interpolants (a reading: the paper writes exact
 integrals of f and g), so that F = M f + G g with G_K = lambda_K L - B^T,
 i.e. G_ij = int lambda_K phi_i phi_j - (n . grad phi_i) phi_j.
 
+Mixed boundaries (section 2, Gamma = Gamma_D + Gamma_N).  The penalty and the
+two Nitsche terms act on Gamma_D only; Gamma_N contributes the load
+int_{K cap Gamma_N} g_N v and nothing to a_h.  Reading: the paper does not say
+how a discrete interface segment is assigned to Gamma_D or Gamma_N.  Here the
+caller gives a nodal indicator chi; a segment is a Neumann segment when the
+bilinear interpolant of chi at the segment's midpoint is > 0, else Dirichlet.
+With g_N replaced by its nodal interpolant the load is GN g_N,
+GN_ij = int_{K cap Gamma_N} phi_i phi_j.  B, L, the penalty and C(K) use the
+Dirichlet segments only; a cell with no Dirichlet segment has lambda_K = 0.
+
 Global matrices live on the full (N+1)^2 node grid (k = i + j (N+1)); rows and
 columns of nodes that touch no active cell are empty.
 """
@@ -91,21 +101,58 @@ def local_eigen_constant(polys, segs):
     return float(scipy.linalg.eigh(Q.T @ Kn @ Q, Q.T @ S @ Q, eigvals_only=True).max())
 
 
-def cut_element(psi4, h, gamma=2.0, rule=geo.STAB_PAPER, lambda_fixed=0.0):
-    """Element matrices (A_K, M_K, G_K) and (type, C, lambda) of one cut cell."""
+def is_neumann_segment(P, Q, chi4):
+    """Segment P -> Q (reference coordinates) is a Neumann segment when the
+    bilinear interpolant of the vertex values chi4 at its midpoint is > 0
+    (the reading in the module docstring).  The interpolant is summed in the
+    vertex order v0..v3."""
+    mx = 0.5 * (P[0] + Q[0])
+    my = 0.5 * (P[1] + Q[1])
+    val = (1.0 - mx) * (1.0 - my) * chi4[0]
+    val += mx * (1.0 - my) * chi4[1]
+    val += mx * my * chi4[2]
+    val += (1.0 - mx) * my * chi4[3]
+    return val > 0.0
+
+
+def split_segments(segs, chi4):
+    """(Dirichlet segments, Neumann segments); all Dirichlet when chi4 is None."""
+    if chi4 is None:
+        return list(segs), []
+    dseg, nseg = [], []
+    for P, Q in segs:
+        (nseg if is_neumann_segment(P, Q, chi4) else dseg).append((P, Q))
+    return dseg, nseg
+
+
+def cut_element(psi4, h, gamma=2.0, rule=geo.STAB_PAPER, lambda_fixed=0.0, chi4=None):
+    """Element matrices (A_K, M_K, G_K, GN_K) and (type, C, lambda) of one cut
+    cell.  chi4: indicator values at v0..v3 (None: the whole interface is
+    Dirichlet)."""
     g = geo.cut_geometry(psi4)
     t, polys, segs, _ = g
-    S, Mr, B, L, _ = reference_integrals(polys, segs)
-    if rule == geo.STAB_FIXED:
+    dseg, nseg = split_segments(segs, chi4)
+    S, Mr, B, L, _ = reference_integrals(polys, dseg)
+    if nseg:
+        _, _, _, LN, _ = reference_integrals([], nseg)
+    else:
+        LN = np.zeros((4, 4))
+    if not dseg and segs:
+        C = 0.0
+        lam = 0.0   # no Dirichlet segment: no penalty
+    elif rule == geo.STAB_FIXED:
         C = 0.0
         lam = lambda_fixed
+    elif rule == geo.STAB_LOCAL_EIG:
+        C = local_eigen_constant(polys, dseg) / h
+        lam = gamma * C
     else:
         C = geo.stabilization_constant(psi4, h, rule, geometry=g)
         lam = gamma * C
     lam_ref = lam * h  # lambda_K L_phys = (lambda_K h) L_ref
     A = S - B - B.T + lam_ref * L
     G = lam_ref * L - B.T
-    return A, Mr * (h * h), G, (t, C, lam)
+    return A, Mr * (h * h), G, LN * h, (t, C, lam)
 
 
 @dataclass
@@ -121,14 +168,18 @@ class Discretisation:
     M: sp.csr_matrix
     G: sp.csr_matrix
     active: np.ndarray     # (n,) bool: vertex of an active cell
+    GN: sp.csr_matrix | None = None  # Neumann load matrix (None: no Neumann segment)
 
     @property
     def n(self):
         return (self.N + 1) ** 2
 
-    def rhs(self, f, g):
-        """F = M f + G g (nodal interpolants of f and g)."""
-        return self.M @ f + self.G @ g
+    def rhs(self, f, g, gN=None):
+        """F = M f + G g (+ GN g_N): nodal interpolants of f, g_D and g_N."""
+        F = self.M @ f + self.G @ g
+        if gN is not None and self.GN is not None:
+            F = F + self.GN @ gN
+        return F
 
     @property
     def cut_cells(self):
@@ -144,8 +195,9 @@ def cell_vertex_indices(N):
 
 
 def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
-             rule=geo.STAB_PAPER, lambda_fixed=0.0, snap=True):
-    """Snap, classify and assemble A, M, G on the full node grid."""
+             rule=geo.STAB_PAPER, lambda_fixed=0.0, snap=True, chi=None):
+    """Snap, classify and assemble A, M, G (and GN when chi, the nodal
+    Neumann indicator, is given) on the full node grid."""
     h = (box[2] - box[0]) / N
     psi_s = geo.snap(psi, h, alpha) if snap else np.asarray(psi, dtype=np.float64).copy()
     psi4 = geo.cell_vertex_values(psi_s, N)
@@ -153,7 +205,8 @@ def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
     V = cell_vertex_indices(N)
     n = (N + 1) ** 2
 
-    rows, cols, aval, mval, gval = [], [], [], [], []
+    chi4 = None if chi is None else geo.cell_vertex_values(np.asarray(chi, dtype=np.float64), N)
+    rows, cols, aval, mval, gval, nval = [], [], [], [], [], []
     S_int, M_int = interior_matrices(h)
     inner = np.nonzero(ctype == geo.INTERNAL)[0]
     if len(inner):
@@ -163,12 +216,14 @@ def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
         aval.append(np.broadcast_to(S_int, (len(inner), 4, 4)).ravel())
         mval.append(np.broadcast_to(M_int, (len(inner), 4, 4)).ravel())
         gval.append(np.zeros(len(inner) * 16))
+        nval.append(np.zeros(len(inner) * 16))
 
     cell_lambda = np.zeros(N * N)
     cell_C = np.zeros(N * N)
     cut = np.nonzero((ctype != geo.EXTERNAL) & (ctype != geo.INTERNAL))[0]
     for c in cut:
-        A_K, M_K, G_K, (_, C, lam) = cut_element(psi4[c], h, gamma, rule, lambda_fixed)
+        A_K, M_K, G_K, N_K, (_, C, lam) = cut_element(
+            psi4[c], h, gamma, rule, lambda_fixed, None if chi4 is None else chi4[c])
         cell_lambda[c] = lam
         cell_C[c] = C
         v = V[c]
@@ -177,6 +232,7 @@ def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
         aval.append(A_K.ravel())
         mval.append(M_K.ravel())
         gval.append(G_K.ravel())
+        nval.append(N_K.ravel())
 
     if rows:
         r = np.concatenate(rows)
@@ -184,14 +240,16 @@ def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
         A = sp.coo_matrix((np.concatenate(aval), (r, c_)), shape=(n, n)).tocsr()
         M = sp.coo_matrix((np.concatenate(mval), (r, c_)), shape=(n, n)).tocsr()
         G = sp.coo_matrix((np.concatenate(gval), (r, c_)), shape=(n, n)).tocsr()
+        GN = sp.coo_matrix((np.concatenate(nval), (r, c_)), shape=(n, n)).tocsr()
+        GN = ((GN + GN.T) * 0.5).tocsr()
         # A and M are symmetric in exact arithmetic; make them so in floating
         # point too (the duplicate summation order may differ between (i,j)
         # and (j,i))
         A = ((A + A.T) * 0.5).tocsr()
         M = ((M + M.T) * 0.5).tocsr()
     else:
-        A = M = G = sp.csr_matrix((n, n))
+        A = M = G = GN = sp.csr_matrix((n, n))
     active = np.zeros(n, dtype=bool)
     active[V[ctype != geo.EXTERNAL].ravel()] = True
     return Discretisation(N, h, tuple(box), psi_s, ctype, cell_lambda, cell_C,
-                          A, M, G, active)
+                          A, M, G, active, GN if chi is not None else None)

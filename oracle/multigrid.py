@@ -120,8 +120,9 @@ def build_hierarchy(disc, coarsest_n=4, dense_limit=4000, rediscretise=None) -> 
     Galerkin condition): psi, the unsnapped fine nodal level set, is injected
     at the coarse nodes (coarse node (I, J) is fine node (2I, 2J)) and
     assembled with the fine grid's parameters kw (gamma, alpha, rule,
-    lambda_fixed) and the coarse cell size; the extra-smoothing set of a
-    coarse level is then the vertices of its own cut cells."""
+    lambda_fixed, and a Neumann indicator chi, injected like psi) and the
+    coarse cell size; the extra-smoothing set of a coarse level is then the
+    vertices of its own cut cells."""
     N = disc.N
     if N % coarsest_n or (N // coarsest_n) & (N // coarsest_n - 1):
         raise ValueError("N must be coarsest_n times a power of two")
@@ -129,6 +130,10 @@ def build_hierarchy(disc, coarsest_n=4, dense_limit=4000, rediscretise=None) -> 
         from . import assembly as asm
         psi_in, akw = rediscretise
         psi_in = np.asarray(psi_in, dtype=np.float64).reshape(N + 1, N + 1)
+        akw = dict(akw)
+        chi_in = akw.pop("chi", None)
+        if chi_in is not None:
+            chi_in = np.asarray(chi_in, dtype=np.float64).reshape(N + 1, N + 1)
     cell_cut = (disc.cell_type != geo.EXTERNAL) & (disc.cell_type != geo.INTERNAL)
     A = disc.A.tocsr()
     levels = []
@@ -155,7 +160,8 @@ def build_hierarchy(disc, coarsest_n=4, dense_limit=4000, rediscretise=None) -> 
             cell_cut = coarsen_cut_cells(cell_cut, N)
         else:
             step = disc.N // (N // 2)
-            dc = asm.assemble(psi_in[::step, ::step].ravel(), N // 2, box=disc.box, **akw)
+            chi_c = None if chi_in is None else chi_in[::step, ::step].ravel()
+            dc = asm.assemble(psi_in[::step, ::step].ravel(), N // 2, box=disc.box, chi=chi_c, **akw)
             A = dc.A.tocsr()
             cell_cut = (dc.cell_type != geo.EXTERNAL) & (dc.cell_type != geo.INTERNAL)
         N //= 2

@@ -63,7 +63,7 @@ def test_cut_cell_identities():
         assert M.sum() == pytest.approx(area, rel=1e-13)                # sum phi_i = 1
         assert L.sum() == pytest.approx(length, rel=1e-13)
         np.testing.assert_allclose(B.sum(axis=1), 0.0, atol=1e-13)     # n . grad 1 = 0
-        A_K, M_K, G_K, (_, C, lam) = asm.cut_element(psi4, h)
+        A_K, M_K, G_K, _, (_, C, lam) = asm.cut_element(psi4, h)
         np.testing.assert_allclose(A_K, A_K.T, atol=1e-13)
         assert lam == pytest.approx(2.0 * C)
         assert M_K.sum() == pytest.approx(area * h * h, rel=1e-13)

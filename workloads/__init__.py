@@ -90,6 +90,34 @@ def ellipse(N, a=0.7, b=0.35, phi=0.3, center=(0.0, 0.0), box=BOX):
     return b * (np.sqrt((xp / a) ** 2 + (yp / b) ** 2) - 1.0)
 
 
+def annulus(N, r1=0.5, r2=0.8, box=BOX):
+    """The annulus of the paper's 2D tests (section 5.3): max(psi1, psi2) with
+    psi1 = r1^2 - r^2 (inner circle) and psi2 = r^2 - r2^2 (outer circle),
+    centred at the origin.  Returns (psi, chi) with the Neumann indicator
+    chi = psi2 - psi1, positive on the outer circle (Neumann) and negative on
+    the inner one (Dirichlet)."""
+    x, y = grid_xy(N, box)
+    r2s = x * x + y * y
+    p1 = r1 * r1 - r2s
+    p2 = r2s - r2 * r2
+    return np.maximum(p1, p2), p2 - p1
+
+
+LEAF_X1 = -0.25 * math.cos(math.pi / 4.0)
+LEAF_X2 = 0.25 * math.sin(math.pi / 4.0)
+
+
+def leaf(N, radius=0.7, box=BOX):
+    """The leaf of the paper's 2D tests (section 5.3): max(R1, R2) - 0.7 with
+    R_m the distance to (x_m, 0), x1 = -0.25 cos(pi/4), x2 = 0.25 sin(pi/4).
+    Returns (psi, chi) with chi = -x: Neumann where x < 0, Dirichlet where
+    x >= 0."""
+    x, y = grid_xy(N, box)
+    R1 = np.sqrt((x - LEAF_X1) ** 2 + y * y)
+    R2 = np.sqrt((x - LEAF_X2) ** 2 + y * y)
+    return np.maximum(R1 - radius, R2 - radius), -x
+
+
 def vertical_line(N, theta, box=UNIT_BOX):
     """x - 1 + (1 - theta) h: the rectangle cut by a vertical line (section 5.3)."""
     x, _ = grid_xy(N, box)
@@ -115,6 +143,14 @@ def mms_flower(N, box=BOX):
     return s + x * x, 2.0 * np.pi ** 2 * s - 2.0
 
 
+def mms_flower_grad(N, box=BOX):
+    """Gradient (u_x, u_y) of the flower's manufactured solution."""
+    x, y = grid_xy(N, box)
+    ux = np.pi * np.cos(np.pi * x) * np.cos(np.pi * y) + 2.0 * x
+    uy = -np.pi * np.sin(np.pi * x) * np.sin(np.pi * y)
+    return ux, uy
+
+
 def adjoint_target(N, box=BOX):
     """u_t = cos(2 pi x) sin(pi y) (the misfit target of the adjoint workload)."""
     x, y = grid_xy(N, box)
@@ -135,6 +171,8 @@ class Problem:
     u_exact: np.ndarray | None = None
     box: tuple = BOX
     meta: dict = field(default_factory=dict)
+    chi: np.ndarray | None = None   # Neumann indicator (None: Dirichlet everywhere)
+    gN: np.ndarray | None = None    # nodal Neumann data
 
 
 def circle_mms(N=64):
@@ -153,6 +191,80 @@ def ellipse_mms(N=4096):
     """Ellipse (0.7, 0.35) rotated 0.3 rad, the flower's manufactured solution."""
     u, f = mms_flower(N)
     return Problem("ellipse_mms", N, ellipse(N), f, u.copy(), u)
+
+
+def annulus_mms(N=256):
+    """Annulus r1 = 0.5 (Dirichlet), r2 = 0.8 (Neumann); the flower's
+    manufactured solution, g_D = u and g_N = (x, y)/r . grad u at the nodes
+    (the outer circle's normal extended off the circle)."""
+    u, f = mms_flower(N)
+    ux, uy = mms_flower_grad(N)
+    x, y = grid_xy(N)
+    r = np.sqrt(x * x + y * y)
+    gN = np.where(r > 0.0, (x * ux + y * uy) / np.where(r > 0.0, r, 1.0), 0.0)
+    psi, chi = annulus(N)
+    return Problem("annulus_mms", N, psi, f, u.copy(), u, chi=chi, gN=gN)
+
+
+def leaf_mms(N=256):
+    """Leaf, Neumann where x < 0; the flower's manufactured solution, g_D = u
+    and g_N = the normal derivative of u on the circle about (x2, 0), which
+    bounds the leaf on that side."""
+    u, f = mms_flower(N)
+    ux, uy = mms_flower_grad(N)
+    x, y = grid_xy(N)
+    R2 = np.sqrt((x - LEAF_X2) ** 2 + y * y)
+    gN = ((x - LEAF_X2) * ux + y * uy) / np.where(R2 > 0.0, R2, 1.0)
+    psi, chi = leaf(N)
+    return Problem("leaf_mms", N, psi, f, u.copy(), u, chi=chi, gN=gN)
+
+
+def linear_strip(N, axis=0, a=-0.61, b=0.57, c0=0.3, c1=1.7, box=BOX):
+    """Strip a < x_axis < b across the box, Dirichlet on the side x_axis = a,
+    Neumann on x_axis = b (chi = x_axis), u = c0 + c1 x_axis, f = 0, g_N = c1.
+    g_D is u plus 5 where x_axis > 0, so that data read on the wrong side
+    shows.  The box edges bound the strip with the natural condition, which
+    u meets (its gradient is parallel to them)."""
+    X = grid_xy(N, box)[axis]
+    psi = np.maximum(a - X, X - b)
+    u = c0 + c1 * X
+    g = u + 5.0 * (X > 0.0)
+    return Problem("linear_strip", N, psi, np.zeros_like(u), g, u, box=box, chi=X.copy(),
+                   gN=np.full_like(u, c1), meta=dict(axis=axis))
+
+
+def linear_rectangle(N, cx=0.03, cy=-0.02, half_t=0.7, half_n=0.35,
+                     c0=0.2, c1=-1.3, neu_t=0.2, box=BOX):
+    """Rectangle |s_t| < half_t, |s_n| < half_n tilted by phi = atan(1/2), with
+    s_n = n . (x - c), s_t = t . (x - c), n = (-sin phi, cos phi),
+    t = (cos phi, sin phi), inside the box.  u = c0 + c1 s_n, f = 0.
+
+    Neumann (g_N = c1) on the middle part of the side s_n = half_n:
+    chi = +1 at the nodes with s_n > 0.1 and |s_t| < neu_t, else -1.
+    g_D = u, plus 5 deep inside the chi = +1 region (s_n > 0.2,
+    |s_t| < neu_t - 3h), where only Neumann cells read it.
+
+    The side s_n = half_n is the line y = x/2 + b; b is moved (through the
+    centre's y) to an odd multiple of h/4, so that every node is at least
+    h/4 cos(phi) from that line and none near it is snapped: the Neumann
+    side stays straight after snapping, which the exact reproduction of u
+    needs."""
+    h = (box[2] - box[0]) / N
+    phi = math.atan(0.5)
+    b0 = cy - 0.5 * cx + half_n / math.cos(phi)
+    lat = 0.5 * h                     # y - x/2 at the nodes: -0.5 + multiples of h/2
+    b = -0.5 + (math.floor((b0 + 0.5) / lat) + 0.5) * lat
+    cy = b + 0.5 * cx - half_n / math.cos(phi)
+    x, y = grid_xy(N, box)
+    dx, dy = x - cx, y - cy
+    sn = -math.sin(phi) * dx + math.cos(phi) * dy
+    st = math.cos(phi) * dx + math.sin(phi) * dy
+    psi = np.maximum(np.abs(sn) - half_n, np.abs(st) - half_t)
+    chi = np.where((sn > 0.1) & (np.abs(st) < neu_t), 1.0, -1.0)
+    u = c0 + c1 * sn
+    g = u + 5.0 * ((sn > 0.2) & (np.abs(st) < neu_t - 3 * h))
+    return Problem("linear_rectangle", N, psi, np.zeros_like(u), g, u, box=box, chi=chi,
+                   gN=np.full_like(u, c1), meta=dict(cx=cx, cy=cy, phi=phi))
 
 
 def batched_draws(count=256, seed=0, sizes=(64, 128, 256, 512)):
