@@ -140,6 +140,25 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* p, void* s
                 mgfem_handle* out);
 
 /*
+ * Mixed Dirichlet/Neumann boundaries (section 2: -lap u = f, u = g_D on
+ * Gamma_D, n . grad u = g_N on Gamma_N; eqs. disc_bil_form and disc_rhs).
+ * As mgfem_setup, plus
+ *  chi_dev : device, (N+1)^2 float64 nodal indicator of the Neumann part
+ *            (read only; NULL: the whole boundary is Dirichlet, as mgfem_setup).
+ * An interface segment of a cut cell belongs to Gamma_N when the bilinear
+ * interpolant of chi at the segment's midpoint is > 0, else to Gamma_D (the
+ * paper leaves this assignment open).  Penalty and Nitsche terms, and C(K),
+ * use the Dirichlet segments only; a cell with no Dirichlet segment has
+ * lambda_K = 0.  The Neumann segments give GN_ij = int_{Gamma_N} phi_i phi_j,
+ * the load matrix of g_N.  Coarse levels assembled on their own grids
+ * (MGFEM_COARSE_REDISCRETISED) take chi at their nodes like psi.
+ * Solve such a handle with mgfem_solve_mixed_bc (mgfem_solve: g_N = 0).
+ * Errors: as mgfem_setup.
+ */
+int mgfem_setup_mixed_bc(const double* psi_dev, const double* chi_dev, int32_t N, const mgfem_params* p,
+                         void* stream, mgfem_handle* out);
+
+/*
  * Solve A u = F with F = M f + G g (Q1 interpolants of f and g; F follows
  * eq. disc_rhs) by repeated cycles until ||F - A u||_inf <= rel_tol ||F||_inf.
  *  f_dev, g_dev  : device (N+1)^2 float64 nodal source and Dirichlet data
@@ -160,6 +179,18 @@ int mgfem_solve(mgfem_handle h, const double* f_dev, const double* g_dev, double
                 int32_t* n_cycles);
 
 /*
+ * mgfem_solve with Neumann data: F = M f + G g_D + GN g_N (eq. disc_rhs, all
+ * three data as Q1 nodal interpolants).
+ *  gN_dev : device (N+1)^2 float64 nodal Neumann data, read at the vertices
+ *           of cells with a Neumann segment; NULL means g_N = 0.  Ignored for
+ *           a handle set up without an indicator.
+ * Other arguments, results and errors as mgfem_solve.
+ */
+int mgfem_solve_mixed_bc(mgfem_handle h, const double* f_dev, const double* gD_dev, const double* gN_dev,
+                         double rel_tol, int32_t max_cycles, uint32_t flags, double* u_dev,
+                         double* res_hist_host, int32_t* n_cycles);
+
+/*
  * Adjoint of the solve: lam = B_k^T dJ/du with B_k the map F -> u of k cycles,
  * run as k transposed cycles from zero (every smoothing phase in reverse
  * order, nu1 and nu2 swapped); k is fixed by rel_tol/max_cycles as in
@@ -173,6 +204,15 @@ int mgfem_solve(mgfem_handle h, const double* f_dev, const double* g_dev, double
 int mgfem_adjoint(mgfem_handle h, const double* dJdu_dev, double rel_tol, int32_t max_cycles,
                   double* lam_dev, double* dJdf_dev, double* dJdg_dev, double* res_hist_host,
                   int32_t* n_cycles);
+
+/*
+ * Gradient with respect to the Neumann data: dJ/dg_N = GN^T lam = GN lam for
+ * the lam of mgfem_adjoint (GN is symmetric; zero for a handle set up
+ * without an indicator).
+ *  lam_dev, dJdgN_dev : device (N+1)^2 float64.  Synchronises.
+ * Errors: INVALID_ARG (NULL pointers, batched handle), HIP.
+ */
+int mgfem_adjoint_neumann(mgfem_handle h, const double* lam_dev, double* dJdgN_dev);
 
 /*
  * Misfit J = 1/2 (u - u_t)^T M (u - u_t) (nodal interpolants) and
@@ -196,7 +236,9 @@ enum mgfem_export_what {
   MGFEM_EXPORT_G = 5,          /* 9 planes of the boundary-load matrix G (level 0 only) */
   MGFEM_EXPORT_NODE_FLAGS = 6, /* per node, as float64: bit 0 active, bit 1 stored
                                   stencil, bit 2 extra-smoothing vertex */
-  MGFEM_EXPORT_RHS = 7         /* F of the last solve, (N+1)^2 float64 */
+  MGFEM_EXPORT_RHS = 7,        /* F of the last solve, (N+1)^2 float64 */
+  MGFEM_EXPORT_GN = 8          /* 9 planes of the Neumann boundary mass GN (level 0 only;
+                                  zero for a handle set up without an indicator) */
 };
 
 /* Copy an internal array of level `level` into device memory dst_dev
@@ -248,7 +290,8 @@ const char* mgfem_last_error(mgfem_handle h);
  * Batched form: `count` independent problems (different psi and N) solved
  * together.  Setup builds every hierarchy; the solve runs all problems'
  * cycles in one persistent cooperative launch per solve, with per-problem
- * convergence.  Parameters are shared by all problems.
+ * convergence.  Parameters are shared by all problems; the whole boundary is
+ * Dirichlet.
  *  psi_dev[i] : device (N[i]+1)^2 float64.  N[i] as in mgfem_setup.
  */
 int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32_t* N,

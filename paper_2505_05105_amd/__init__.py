@@ -6,6 +6,9 @@ and adjoint runs in the library's HIP kernels (see include/mgfem.h).
     solver = Solver(psi, N)                  # psi: (N+1)^2 nodal level set
     u, hist = solver.solve(f, g, tol=1e-10)  # u: torch float64 on the GPU
     u = GhostFEMSolve.apply(f, g, solver)    # differentiable in f and g
+
+    solver = Solver(psi, N, chi=chi)         # Neumann where chi > 0 (mixed boundaries)
+    u, hist = solver.solve(f, gD, gN=gN)
 """
 from __future__ import annotations
 
@@ -38,9 +41,10 @@ def _dev(x, device, n=None):
 
 
 class Solver:
-    """One level set, one hierarchy (mgfem_setup / mgfem_destroy)."""
+    """One level set, one hierarchy (mgfem_setup / mgfem_destroy).  With chi,
+    the nodal Neumann indicator, mixed boundaries (mgfem_setup_mixed_bc)."""
 
-    def __init__(self, psi, N, device="cuda:0", **params):
+    def __init__(self, psi, N, device="cuda:0", chi=None, **params):
         self.N = int(N)
         self.n = (self.N + 1) ** 2
         self.device = torch.device(device)
@@ -49,8 +53,14 @@ class Solver:
         self._psi = _dev(psi, self.device, self.n)
         h = C.c_void_p()
         L = _lib.lib()
-        rc = L.mgfem_setup(self._psi.data_ptr(), self.N, C.byref(self.params),
-                           C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if chi is None:
+            rc = L.mgfem_setup(self._psi.data_ptr(), self.N, C.byref(self.params),
+                               C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        else:
+            chi_t = _dev(chi, self.device, self.n)
+            rc = L.mgfem_setup_mixed_bc(self._psi.data_ptr(), chi_t.data_ptr(), self.N,
+                                        C.byref(self.params), C.c_void_p(self.stream.cuda_stream),
+                                        C.byref(h))
         _lib.check(rc, None)
         self.handle = h
         self.last_cycles = 0
@@ -77,16 +87,19 @@ class Solver:
         sizes = {_lib.EXPORT_PSI: (self.N + 1) ** 2, _lib.EXPORT_CELL_TYPE: self.N ** 2,
                  _lib.EXPORT_CELL_LAMBDA: self.N ** 2, _lib.EXPORT_A: 9 * (Nl + 1) ** 2,
                  _lib.EXPORT_M: 9 * (Nl + 1) ** 2, _lib.EXPORT_G: 9 * (Nl + 1) ** 2,
-                 _lib.EXPORT_NODE_FLAGS: (Nl + 1) ** 2, _lib.EXPORT_RHS: (self.N + 1) ** 2}
+                 _lib.EXPORT_NODE_FLAGS: (Nl + 1) ** 2, _lib.EXPORT_RHS: (self.N + 1) ** 2,
+                 _lib.EXPORT_GN: 9 * (Nl + 1) ** 2}
         out = torch.empty(sizes[what], dtype=torch.float64, device=self.device)
         _lib.check(_lib.lib().mgfem_export(self.handle, what, level, out.data_ptr()), self.handle)
         return out
 
     # -- solves --------------------------------------------------------------
-    def solve(self, f, g, tol=1e-10, max_cycles=50, u0=None, out=None, raise_on_fail=True):
-        """Returns (u, hist) with hist[m] = ||F - A u_m||_inf, m = 0..cycles."""
+    def solve(self, f, g, tol=1e-10, max_cycles=50, u0=None, out=None, raise_on_fail=True, gN=None):
+        """Returns (u, hist) with hist[m] = ||F - A u_m||_inf, m = 0..cycles.
+        g is the Dirichlet data, gN the Neumann data (mixed boundaries)."""
         f = _dev(f, self.device, self.n)
         g = _dev(g, self.device, self.n)
+        gN = None if gN is None else _dev(gN, self.device, self.n)
         flags = 0
         if out is None:
             out = torch.empty(self.n, dtype=torch.float64, device=self.device)
@@ -95,9 +108,14 @@ class Solver:
             flags = _lib.SOLVE_WARM_START
         hist = np.zeros(max_cycles + 1)
         ncyc = C.c_int32(0)
-        rc = _lib.lib().mgfem_solve(self.handle, f.data_ptr(), g.data_ptr(), float(tol),
-                                    int(max_cycles), flags, out.data_ptr(),
-                                    hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ncyc))
+        hp = hist.ctypes.data_as(C.POINTER(C.c_double))
+        if gN is None:
+            rc = _lib.lib().mgfem_solve(self.handle, f.data_ptr(), g.data_ptr(), float(tol),
+                                        int(max_cycles), flags, out.data_ptr(), hp, C.byref(ncyc))
+        else:
+            rc = _lib.lib().mgfem_solve_mixed_bc(self.handle, f.data_ptr(), g.data_ptr(), gN.data_ptr(),
+                                                 float(tol), int(max_cycles), flags, out.data_ptr(), hp,
+                                                 C.byref(ncyc))
         self.last_status = rc
         self.last_cycles = ncyc.value
         if raise_on_fail:
@@ -117,6 +135,14 @@ class Solver:
                                       hist.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ncyc))
         _lib.check(rc, self.handle, allow=(_lib.OK, _lib.ERR_NOT_CONVERGED))
         return df, dg, lam, hist[: ncyc.value + 1]
+
+    def neumann_gradient(self, lam):
+        """dJ/dg_N = GN^T lam for the lam returned by adjoint()."""
+        lam = _dev(lam, self.device, self.n)
+        out = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        _lib.check(_lib.lib().mgfem_adjoint_neumann(self.handle, lam.data_ptr(), out.data_ptr()),
+                   self.handle)
+        return out
 
     def misfit(self, u, ut):
         """J = 1/2 (u - u_t)^T M (u - u_t) and dJ/du = M (u - u_t)."""

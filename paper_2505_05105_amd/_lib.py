@@ -20,13 +20,14 @@ CYCLE_V, CYCLE_W, CYCLE_TWO_GRID = 1, 2, 3
 COARSE_GALERKIN, COARSE_REDISCRETISED = 0, 1
 SOLVE_WARM_START = 1
 EXPORT_PSI, EXPORT_CELL_TYPE, EXPORT_CELL_LAMBDA, EXPORT_A, EXPORT_M, EXPORT_G, \
-    EXPORT_NODE_FLAGS, EXPORT_RHS = range(8)
+    EXPORT_NODE_FLAGS, EXPORT_RHS, EXPORT_GN = range(9)
 
 EXPORTED = (
     "mgfem_default_params", "mgfem_setup", "mgfem_solve", "mgfem_adjoint", "mgfem_misfit",
     "mgfem_query", "mgfem_export", "mgfem_level_n", "mgfem_smooth", "mgfem_destroy",
     "mgfem_status_string", "mgfem_last_error", "mgfem_setup_batched", "mgfem_solve_batched",
     "mgfem_level_counts", "mgfem_profile", "mgfem_profile_read", "mgfem_batched_tile",
+    "mgfem_setup_mixed_bc", "mgfem_solve_mixed_bc", "mgfem_adjoint_neumann",
 )
 
 
@@ -65,7 +66,10 @@ def lib():
     sig = {
         "mgfem_default_params": (C.c_int, [C.POINTER(Params)]),
         "mgfem_setup": (C.c_int, [P, I32, C.POINTER(Params), VP, C.POINTER(P)]),
+        "mgfem_setup_mixed_bc": (C.c_int, [P, P, I32, C.POINTER(Params), VP, C.POINTER(P)]),
         "mgfem_solve": (C.c_int, [P, P, P, D, I32, U32, P, DP, C.POINTER(I32)]),
+        "mgfem_solve_mixed_bc": (C.c_int, [P, P, P, P, D, I32, U32, P, DP, C.POINTER(I32)]),
+        "mgfem_adjoint_neumann": (C.c_int, [P, P, P]),
         "mgfem_adjoint": (C.c_int, [P, P, D, I32, P, P, P, DP, C.POINTER(I32)]),
         "mgfem_misfit": (C.c_int, [P, P, P, DP, P]),
         "mgfem_query": (C.c_int, [P, C.POINTER(Info)]),

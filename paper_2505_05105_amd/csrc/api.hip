@@ -221,8 +221,12 @@ const char* mgfem_last_error(mgfem_handle h) {
   return h ? h->last_error.c_str() : g_setup_error.c_str();
 }
 
-int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void* stream,
-                mgfem_handle* out) {
+}  // extern "C"
+
+namespace {
+
+int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mgfem_params* pin, void* stream,
+               mgfem_handle* out) {
   if (!out) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!psi_dev) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "psi_dev is NULL");
@@ -291,9 +295,9 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
     const char* env = std::getenv("MGFEM_NO_GRAPHS");
     c->use_graphs = !(env && env[0] && env[0] != '0');
   }
-  rc = setup_geometry(c, psi_dev);
+  rc = setup_geometry(c, psi_dev, chi_dev);
   if (rc != MGFEM_OK) return bail(rc);
-  rc = setup_hierarchy(c, psi_dev);
+  rc = setup_hierarchy(c, psi_dev, chi_dev);
   if (rc != MGFEM_OK) return bail(rc);
   SETUP_TRY(hipEventRecord(e1, c->s));
   Stats st{};
@@ -335,6 +339,19 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* pin, void*
 #undef SETUP_TRY
   *out = c;
   return MGFEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* p, void* stream, mgfem_handle* out) {
+  return setup_impl(psi_dev, nullptr, N, p, stream, out);
+}
+
+int mgfem_setup_mixed_bc(const double* psi_dev, const double* chi_dev, int32_t N, const mgfem_params* p,
+                         void* stream, mgfem_handle* out) {
+  return setup_impl(psi_dev, chi_dev, N, p, stream, out);
 }
 
 int mgfem_query(mgfem_handle h, mgfem_info* info) {
@@ -616,13 +633,21 @@ extern "C" {
 int mgfem_solve(mgfem_handle c, const double* f_dev, const double* g_dev, double rel_tol,
                 int32_t max_cycles, uint32_t flags, double* u_dev, double* res_hist_host,
                 int32_t* n_cycles) {
+  return mgfem_solve_mixed_bc(c, f_dev, g_dev, nullptr, rel_tol, max_cycles, flags, u_dev, res_hist_host,
+                              n_cycles);
+}
+
+int mgfem_solve_mixed_bc(mgfem_handle c, const double* f_dev, const double* gD_dev, const double* gN_dev,
+                         double rel_tol, int32_t max_cycles, uint32_t flags, double* u_dev,
+                         double* res_hist_host, int32_t* n_cycles) {
+  const double* g_dev = gD_dev;
   if (!c) return MGFEM_ERR_INVALID_ARG;
   if (c->batched_member) return fail(c, MGFEM_ERR_INVALID_ARG, "batched handle: use mgfem_solve_batched");
   if (!f_dev || !g_dev || !u_dev || max_cycles < 0)
     return fail(c, MGFEM_ERR_INVALID_ARG, "f, g and u must be device pointers; max_cycles >= 0");
   const bool warm = (flags & MGFEM_SOLVE_WARM_START) != 0;
   if (warm) launch_mask_inactive(c, u_dev);
-  launch_rhs(c, f_dev, g_dev, c->F);
+  launch_rhs(c, f_dev, g_dev, gN_dev, c->F);
   MGFEM_HIP_TRY(hipGetLastError());
   double bnorm, l2;
   int rc = read_norm(c, bnorm, l2);
@@ -652,6 +677,16 @@ int mgfem_adjoint(mgfem_handle c, const double* dJdu_dev, double rel_tol, int32_
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   return rc;
+}
+
+int mgfem_adjoint_neumann(mgfem_handle c, const double* lam_dev, double* dJdgN_dev) {
+  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (c->batched_member) return fail(c, MGFEM_ERR_INVALID_ARG, "batched handle");
+  if (!lam_dev || !dJdgN_dev) return fail(c, MGFEM_ERR_INVALID_ARG, "lam and dJdgN must be device pointers");
+  launch_gn_apply(c, lam_dev, dJdgN_dev);  // GN^T = GN
+  MGFEM_HIP_TRY(hipGetLastError());
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return MGFEM_OK;
 }
 
 int mgfem_misfit(mgfem_handle c, const double* u_dev, const double* ut_dev, double* J_host,
@@ -749,6 +784,11 @@ int mgfem_export(mgfem_handle c, int32_t what, int32_t level, double* dst) {
     case MGFEM_EXPORT_G:
       if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
       launch_copy(c, dst, c->G, 9 * n);
+      break;
+    case MGFEM_EXPORT_GN:
+      if (!l0) return fail(c, MGFEM_ERR_INVALID_ARG, "level 0 only");
+      if (c->GN) launch_copy(c, dst, c->GN, 9 * n);
+      else launch_zero(c, dst, 9 * n);
       break;
     case MGFEM_EXPORT_NODE_FLAGS: launch_u8_to_f64(c, L.flags, dst, n); break;
     case MGFEM_EXPORT_RHS:

@@ -200,17 +200,19 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict_
   }
 }
 
-// F = M f + G g (section 2, the discrete load) in two parts.  The vertices of
-// cut cells (the rows that differ from the interior ones) take their M and G
-// rows from one contiguous gathered array (18 values per vertex, in cut-list
-// order): k_cut_rows.  Every other node of the box of active nodes is done by
+// F = M f + G g (+ GN g_N on mixed boundaries; section 2, the discrete load)
+// in two parts.  The vertices of cut cells (the rows that differ from the
+// interior ones) take their M and G rows from one contiguous gathered array
+// (18 values per vertex, in cut-list order; the GN rows, 9 per vertex, from a
+// second one): k_cut_rows.  Every other node of the box of active nodes is done by
 // k_rhs: an active row whose four cells are interior has the constant Q1 mass
 // stencil h^2/36 [1 4 1; 4 16 4; 1 4 1] and no boundary term; k_rhs also
 // reduces (max |F|, sum F^2) over all active nodes, reading F at the cut
 // vertices, so k_cut_rows runs first.
 __global__ void k_cut_rows(const int* __restrict__ cut_list, int ncut, const double* __restrict__ rows,
-                           const double* __restrict__ x, const double* __restrict__ g, double* __restrict__ y,
-                           int N) {
+                           const double* __restrict__ x, const double* __restrict__ g,
+                           const double* __restrict__ rows_n, const double* __restrict__ gn,
+                           double* __restrict__ y, int N) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ncut) return;
   const int s = N + 1;
@@ -225,6 +227,29 @@ __global__ void k_cut_rows(const int* __restrict__ cut_list, int ncut, const dou
     const double m = r[p], gg = r[9 + p];
     if (m != 0.0) acc += m * x[kk];
     if (g && gg != 0.0) acc += gg * g[kk];
+    if (gn) {
+      const double w = rows_n[9 * (int64_t)t + p];
+      if (w != 0.0) acc += w * gn[kk];
+    }
+  }
+  y[k] = acc;
+}
+
+// y = GN x at the vertices of cut cells (GN is symmetric and vanishes
+// elsewhere; y must be zero off them)
+__global__ void k_cut_rows9(const int* __restrict__ cut_list, int ncut, const double* __restrict__ rows_n,
+                            const double* __restrict__ x, double* __restrict__ y, int N) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ncut) return;
+  const int s = N + 1;
+  const int64_t k = cut_list[t];
+  const int i = (int)(k % s), j = (int)(k / s);
+  double acc = 0.0;
+  for (int p = 0; p < 9; ++p) {
+    const int ii = i + p % 3 - 1, jj = j + p / 3 - 1;
+    if (ii < 0 || jj < 0 || ii > N || jj > N) continue;
+    const double w = rows_n[9 * (int64_t)t + p];
+    if (w != 0.0) acc += w * x[ii + (int64_t)jj * s];
   }
   y[k] = acc;
 }
@@ -274,8 +299,9 @@ __device__ inline double plane_row(const double* __restrict__ S, const double* _
 }
 
 __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ M, const double* __restrict__ G,
-                                             const uint8_t* __restrict__ fl, const double* __restrict__ f,
-                                             const double* __restrict__ g, double* __restrict__ F, int N,
+                                             const double* __restrict__ GN, const uint8_t* __restrict__ fl,
+                                             const double* __restrict__ f, const double* __restrict__ g,
+                                             const double* __restrict__ gn, double* __restrict__ F, int N,
                                              double hh36, int i0, int j0, int ni, int nj,
                                              double* __restrict__ part) {
   __shared__ double sv[kSN];
@@ -295,7 +321,10 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ M, const
     if (fk & kFlagActive) {
       if (!(fk & kFlagStored)) acc = mass_row(sv, threadIdx.x + 1 + (rep + 1) * kSW, hh36);
       else if (fk & kFlagCut) acc = F[k];  // from k_cut_rows
-      else acc = plane_row(M, f, n, k, i, j, N, s) + plane_row(G, g, n, k, i, j, N, s);
+      else {
+        acc = plane_row(M, f, n, k, i, j, N, s) + plane_row(G, g, n, k, i, j, N, s);
+        if (gn) acc += plane_row(GN, gn, n, k, i, j, N, s);
+      }
     }
     if (!(fk & kFlagActive) || !(fk & kFlagStored) || !(fk & kFlagCut)) F[k] = acc;
     mx = nanmax(mx, fabs(acc));
@@ -389,16 +418,17 @@ inline unsigned nblk(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); 
 
 }  // namespace
 
-void launch_rhs(mgfem_ctx* c, const double* f, const double* g, double* F) {
+void launch_rhs(mgfem_ctx* c, const double* f, const double* g, const double* gN, double* F) {
   const Level& L = c->lv[0];
   const int ncut = L.cut_off[4];
+  if (!c->GN) gN = nullptr;  // no Neumann segment: the Neumann data are not read
   if (ncut > 0)
     hipLaunchKernelGGL(k_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->cut_rows, f, g,
-                       F, c->N);
+                       (const double*)c->cut_rows_n, gN, F, c->N);
   const int ni = L.bbox[1] - L.bbox[0] + 1, nj = L.bbox[3] - L.bbox[2] + 1;
   const dim3 grid((unsigned)std::max(1, (ni + 255) / 256), (unsigned)std::max(1, (nj + 3) / 4));
   const int nb = (int)(grid.x * grid.y);
-  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, c->s, c->M, c->G, L.flags, f, g, F, c->N,
+  hipLaunchKernelGGL(k_rhs, grid, dim3(256), 0, c->s, c->M, c->G, (const double*)c->GN, L.flags, f, g, gN, F, c->N,
                      c->h * c->h / 36.0, L.bbox[0], L.bbox[2], ni, nj, c->red_partial);
   c->red_seq += 1.0;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->s, c->red_partial, nb, c->red_out, c->red_host,
@@ -419,15 +449,17 @@ void launch_outer(mgfem_ctx* c, const double* u, const float* e, double* u_out, 
 }
 
 namespace {
-// the M and G rows of every cut-cell vertex of level 0, in cut-list order
+// the M and G rows (and GN rows) of every cut-cell vertex of level 0, in cut-list order
 __global__ void k_gather_cut_rows(const int* __restrict__ cut_list, int ncut, const double* __restrict__ M,
-                                  const double* __restrict__ G, int64_t n, double* __restrict__ rows) {
+                                  const double* __restrict__ G, const double* __restrict__ GN, int64_t n,
+                                  double* __restrict__ rows, double* __restrict__ rows_n) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ncut) return;
   const int64_t k = cut_list[t];
   for (int p = 0; p < 9; ++p) {
     rows[18 * (int64_t)t + p] = M[p * n + k];
     rows[18 * (int64_t)t + 9 + p] = G[p * n + k];
+    if (GN) rows_n[9 * (int64_t)t + p] = GN[p * n + k];
   }
 }
 }  // namespace
@@ -436,9 +468,10 @@ int build_cut_rows(mgfem_ctx* c) {
   const Level& L = c->lv[0];
   const int ncut = L.cut_off[4];
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cut_rows, 18 * (size_t)std::max(1, ncut)));
+  if (c->GN) MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cut_rows_n, 9 * (size_t)std::max(1, ncut)));
   if (ncut > 0)
     hipLaunchKernelGGL(k_gather_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->M, c->G,
-                       L.n, c->cut_rows);
+                       (const double*)c->GN, L.n, c->cut_rows, c->cut_rows_n);
   MGFEM_HIP_TRY(hipGetLastError());
   return MGFEM_OK;
 }
@@ -452,7 +485,16 @@ void launch_mass_apply(mgfem_ctx* c, const double* x, double* y) {
   const int ncut = L.cut_off[4];
   if (ncut > 0)
     hipLaunchKernelGGL(k_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->cut_rows, x,
-                       (const double*)nullptr, y, N);
+                       (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, y, N);
+}
+
+void launch_gn_apply(mgfem_ctx* c, const double* x, double* y) {
+  const Level& L = c->lv[0];
+  launch_zero(c, y, L.n);
+  const int ncut = L.cut_off[4];
+  if (c->GN && ncut > 0)
+    hipLaunchKernelGGL(k_cut_rows9, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut,
+                       (const double*)c->cut_rows_n, x, y, c->N);
 }
 
 void launch_gt_apply(mgfem_ctx* c, const double* x, double* y) {

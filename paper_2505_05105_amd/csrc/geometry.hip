@@ -10,6 +10,13 @@
 // seven-point triangle rule over a fan of triangles from the polygon's vertex
 // mean, and four-point Gauss-Lobatto on the segments (degree 5), which covers
 // the degree-4 mass and penalty integrands.
+//
+// Mixed boundaries (section 2): given a nodal indicator chi, a segment whose
+// midpoint has a positive bilinear interpolant of chi belongs to Gamma_N (the
+// paper leaves the assignment of discrete segments open; this is the rule the
+// library uses).  Penalty, Nitsche terms and C(K) use the Dirichlet segments
+// only; the Neumann segments give the boundary mass GN of the load
+// int_{Gamma_N} g_N v; a cell with no Dirichlet segment has lambda_K = 0.
 #include <cmath>
 
 #include "mgfem_internal.h"
@@ -51,6 +58,7 @@ struct CutCell {
   P2 poly[2][6];
   int nseg;
   P2 sp[2], sq[2];   // segment endpoints; the piece lies to the left of sp -> sq
+  int neu[2];        // 1: the segment lies on the Neumann part of the boundary
   double theta[4];   // cut fraction of edge e from its inside end, or -1
 };
 
@@ -72,6 +80,7 @@ __host__ __device__ void cut_cell(const double ps[4], CutCell& cc) {
   cc.type = classify4(ps);
   cc.npoly = 0;
   cc.nseg = 0;
+  cc.neu[0] = cc.neu[1] = 0;
   P2 cp[4];
   bool in[4];
   for (int m = 0; m < 4; ++m) in[m] = ps[m] < 0.0;
@@ -139,6 +148,28 @@ __host__ __device__ void cut_cell(const double ps[4], CutCell& cc) {
   }
 }
 
+// Mark the Neumann segments: bilinear interpolant of the vertex values chi at
+// the segment midpoint > 0, summed in vertex order without contraction so that
+// the decision is the one a plain float64 evaluation takes.
+__host__ __device__ void mark_neumann(CutCell& cc, const double chi[4]) {
+#pragma clang fp contract(off)
+  for (int s = 0; s < cc.nseg; ++s) {
+    const double mx = 0.5 * (cc.sp[s].x + cc.sq[s].x), my = 0.5 * (cc.sp[s].y + cc.sq[s].y);
+    double v = (1.0 - mx) * (1.0 - my) * chi[0];
+    v += mx * (1.0 - my) * chi[1];
+    v += mx * my * chi[2];
+    v += (1.0 - mx) * my * chi[3];
+    cc.neu[s] = v > 0.0 ? 1 : 0;
+  }
+}
+
+// the cell has segments and every one of them is a Neumann segment
+__host__ __device__ inline bool all_neumann(const CutCell& cc) {
+  for (int s = 0; s < cc.nseg; ++s)
+    if (!cc.neu[s]) return false;
+  return cc.nseg > 0;
+}
+
 // C(K) h for a triangle with cut sides t1 h, t2 h (eq. c_triangle).
 __host__ __device__ double chat_triangle(double t1, double t2) {
   double s2 = t1 * t1 + t2 * t2;
@@ -202,14 +233,15 @@ __host__ __device__ inline void radon(int q, double& l1, double& l2, double& l3,
   l3 = r == 2 ? b : a;
 }
 
-// Full 4x4 reference integrals of a cut cell (h = 1).
+// Full 4x4 reference integrals of a cut cell (h = 1); L, B, Kn over the
+// Dirichlet segments, LN (boundary mass) over the Neumann segments.
 struct CellInt {
-  double S[4][4], Mm[4][4], L[4][4], B[4][4], Kn[4][4];
+  double S[4][4], Mm[4][4], L[4][4], B[4][4], Kn[4][4], LN[4][4];
 };
 
 __host__ __device__ void cell_integrals(const CutCell& cc, CellInt& I) {
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) I.S[i][j] = I.Mm[i][j] = I.L[i][j] = I.B[i][j] = I.Kn[i][j] = 0.0;
+    for (int j = 0; j < 4; ++j) I.S[i][j] = I.Mm[i][j] = I.L[i][j] = I.B[i][j] = I.Kn[i][j] = I.LN[i][j] = 0.0;
   for (int q = 0; q < cc.npoly; ++q) {
     int nv = cc.nv[q];
     P2 cen{0.0, 0.0};
@@ -249,6 +281,16 @@ __host__ __device__ void cell_integrals(const CutCell& cc, CellInt& I) {
     double len = sqrt(dx * dx + dy * dy);
     if (len == 0.0) continue;
     double nx = dy / len, ny = -dx / len;  // outward: to the right of P -> Q
+    if (cc.neu[sgi]) {
+      for (int k = 0; k < 4; ++k) {
+        double ph[4];
+        q1_val(P.x + gt[k] * dx, P.y + gt[k] * dy, ph);
+        double wl = gw[k] * len;
+        for (int i = 0; i < 4; ++i)
+          for (int j = 0; j < 4; ++j) I.LN[i][j] += wl * (ph[i] * ph[j]);
+      }
+      continue;
+    }
     for (int k = 0; k < 4; ++k) {
       double x = P.x + gt[k] * dx, y = P.y + gt[k] * dy;
       double ph[4], gx[4], gy[4], dn[4];
@@ -386,8 +428,8 @@ __device__ inline void load_cell_psi(const double* psi, int stride, int ci, int 
   ps[3] = psi[k0 + stride];
 }
 
-__global__ void k_classify(const double* __restrict__ psi, int N, mgfem_params p, double h,
-                           uint8_t* __restrict__ ctype, double* __restrict__ clam,
+__global__ void k_classify(const double* __restrict__ psi, const double* __restrict__ chi, int N,
+                           mgfem_params p, double h, uint8_t* __restrict__ ctype, double* __restrict__ clam,
                            uint8_t* __restrict__ cellcut, Stats* st) {
   __shared__ unsigned int cnt[7];
   __shared__ unsigned long long mint, maxl;
@@ -408,6 +450,11 @@ __global__ void k_classify(const double* __restrict__ psi, int N, mgfem_params p
     if (t != kExternal && t != kInternal) {
       CutCell cc;
       cut_cell(ps, cc);
+      if (chi) {
+        double cs[4];
+        load_cell_psi(chi, N + 1, ci, cj, cs);
+        mark_neumann(cc, cs);
+      }
       double chat_eig = 0.0;
       if (p.stab_rule == MGFEM_STAB_LOCAL_EIG) {
         CellInt I;
@@ -415,7 +462,7 @@ __global__ void k_classify(const double* __restrict__ psi, int N, mgfem_params p
         chat_eig = chat_local_eig(I);
       }
       double lh = lambda_h_rule(ps, cc.theta, t, p.stab_rule, p.gamma, p.lambda_fixed, h, chat_eig);
-      lam = lh / h;
+      lam = all_neumann(cc) ? 0.0 : lh / h;
       double tmin = 2.0;
       for (int e = 0; e < 4; ++e)
         if (cc.theta[e] >= 0.0) tmin = fmin(tmin, cc.theta[e]);
@@ -441,10 +488,11 @@ __constant__ int kVx[4] = {0, 1, 1, 0};
 __constant__ int kVy[4] = {0, 0, 1, 1};
 
 // Gather the rows of A, M, G of every node from its (up to) four cells.
-__global__ void k_assemble(const double* __restrict__ psi, int N, mgfem_params p, double h,
-                           const uint8_t* __restrict__ ctype, const double* __restrict__ clam,
-                           double* __restrict__ A, double* __restrict__ Mm,
-                           double* __restrict__ G, uint8_t* __restrict__ flags, Stats* st) {
+__global__ void k_assemble(const double* __restrict__ psi, const double* __restrict__ chi, int N,
+                           mgfem_params p, double h, const uint8_t* __restrict__ ctype,
+                           const double* __restrict__ clam, double* __restrict__ A, double* __restrict__ Mm,
+                           double* __restrict__ G, double* __restrict__ GN, uint8_t* __restrict__ flags,
+                           Stats* st) {
   __shared__ unsigned int nact;
   if (threadIdx.x == 0) nact = 0;
   __syncthreads();
@@ -453,8 +501,8 @@ __global__ void k_assemble(const double* __restrict__ psi, int N, mgfem_params p
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k < n) {
     int i = (int)(k % stride), j = (int)(k / stride);
-    double a[9], m[9], g[9];
-    for (int q = 0; q < 9; ++q) a[q] = m[q] = g[q] = 0.0;
+    double a[9], m[9], g[9], gn[9];
+    for (int q = 0; q < 9; ++q) a[q] = m[q] = g[q] = gn[q] = 0.0;
     bool active = false, regular = true;
     // cells around the node, with the node's local vertex number in each
     const int cdx[4] = {-1, 0, 0, -1}, cdy[4] = {-1, -1, 0, 0}, loc[4] = {2, 3, 0, 1};
@@ -484,6 +532,11 @@ __global__ void k_assemble(const double* __restrict__ psi, int N, mgfem_params p
         load_cell_psi(psi, stride, ci, cj, ps);
         CutCell cc;
         cut_cell(ps, cc);
+        if (chi) {
+          double cs[4];
+          load_cell_psi(chi, stride, ci, cj, cs);
+          mark_neumann(cc, cs);
+        }
         CellInt I;
         cell_integrals(cc, I);
         double lh = clam[c] * h;  // lambda_K h
@@ -497,6 +550,7 @@ __global__ void k_assemble(const double* __restrict__ psi, int N, mgfem_params p
           m[pl] += (h * h) * I.Mm[lv][mm];
           // G_ij = lambda L_ij - int (n . grad phi_i) phi_j
           g[pl] += lh * I.L[lv][mm] - I.B[mm][lv];
+          gn[pl] += h * I.LN[lv][mm];  // int_{Gamma_N} phi_i phi_j
         }
       }
     }
@@ -504,6 +558,7 @@ __global__ void k_assemble(const double* __restrict__ psi, int N, mgfem_params p
       A[q * n + k] = a[q];
       if (Mm) Mm[q * n + k] = m[q];  // mass and boundary load: finest level only
       if (G) G[q * n + k] = g[q];
+      if (GN) GN[q * n + k] = gn[q];
     }
     uint8_t f = 0;
     if (active) f |= kFlagActive;
@@ -526,13 +581,13 @@ __global__ void k_inject(const double* __restrict__ psi_in, int N0, int step, do
 
 }  // namespace
 
-int assemble_level(mgfem_ctx* c, int l, const double* psi_in) {
+int assemble_level(mgfem_ctx* c, int l, const double* psi_in, const double* chi_in) {
   Level& L = c->lv[l];
   const int N = L.N;
   const int64_t n = L.n, nc = (int64_t)N * N;
   const double h = (c->p.x_hi - c->p.x_lo) / N;
   const int tb = 256;
-  double *raw = nullptr, *psi = nullptr, *lam = nullptr;
+  double *raw = nullptr, *psi = nullptr, *lam = nullptr, *chi = nullptr;
   uint8_t* ct = nullptr;
   Stats* st = nullptr;  // statistics of the coarse grids are not reported
   MGFEM_HIP_TRY(ctx_alloc_t(c, &raw, n));
@@ -540,6 +595,7 @@ int assemble_level(mgfem_ctx* c, int l, const double* psi_in) {
   MGFEM_HIP_TRY(ctx_alloc_t(c, &lam, nc));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &ct, nc));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &st, 1));
+  if (chi_in) MGFEM_HIP_TRY(ctx_alloc_t(c, &chi, n));
   {
     Stats init{};
     init.min_theta_bits = 0x7ff0000000000000ull;
@@ -550,18 +606,21 @@ int assemble_level(mgfem_ctx* c, int l, const double* psi_in) {
   MGFEM_HIP_TRY(ctx_alloc_t(c, &L.cellcut, nc));
   hipLaunchKernelGGL(k_inject, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, psi_in, c->N, c->N / N, raw,
                      N);
+  if (chi_in)
+    hipLaunchKernelGGL(k_inject, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, chi_in, c->N, c->N / N,
+                       chi, N);
   hipLaunchKernelGGL(k_snap, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)raw, psi, n,
                      pow(h, c->p.snap_alpha), st);
-  hipLaunchKernelGGL(k_classify, dim3((unsigned)((nc + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)psi, N,
-                     c->p, h, ct, lam, L.cellcut, st);
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)psi, N,
-                     c->p, h, (const uint8_t*)ct, (const double*)lam, L.A, (double*)nullptr, (double*)nullptr,
-                     L.flags, st);
+  hipLaunchKernelGGL(k_classify, dim3((unsigned)((nc + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)psi,
+                     (const double*)chi, N, c->p, h, ct, lam, L.cellcut, st);
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)psi,
+                     (const double*)chi, N, c->p, h, (const uint8_t*)ct, (const double*)lam, L.A, (double*)nullptr,
+                     (double*)nullptr, (double*)nullptr, L.flags, st);
   MGFEM_HIP_TRY(hipGetLastError());
   return MGFEM_OK;
 }
 
-int setup_geometry(mgfem_ctx* c, const double* psi_in) {
+int setup_geometry(mgfem_ctx* c, const double* psi_in, const double* chi_in) {
   const int N = c->N;
   const int64_t n = (int64_t)(N + 1) * (N + 1), nc = (int64_t)N * N;
   Level& L0 = c->lv[0];
@@ -570,6 +629,7 @@ int setup_geometry(mgfem_ctx* c, const double* psi_in) {
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cell_lambda, nc));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->M, 9 * n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->G, 9 * n));
+  if (chi_in) MGFEM_HIP_TRY(ctx_alloc_t(c, &c->GN, 9 * n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &L0.A, 9 * n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &L0.flags, n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &L0.cellcut, nc));
@@ -577,10 +637,10 @@ int setup_geometry(mgfem_ctx* c, const double* psi_in) {
   double thr = pow(c->h, c->p.snap_alpha);
   hipLaunchKernelGGL(k_snap, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, psi_in, c->psi,
                      n, thr, c->stats);
-  hipLaunchKernelGGL(k_classify, dim3((unsigned)((nc + tb - 1) / tb)), dim3(tb), 0, c->s, c->psi, N,
+  hipLaunchKernelGGL(k_classify, dim3((unsigned)((nc + tb - 1) / tb)), dim3(tb), 0, c->s, c->psi, chi_in, N,
                      c->p, c->h, c->cell_type, c->cell_lambda, L0.cellcut, c->stats);
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, c->psi, N,
-                     c->p, c->h, c->cell_type, c->cell_lambda, L0.A, c->M, c->G, L0.flags,
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, c->psi, chi_in, N,
+                     c->p, c->h, c->cell_type, c->cell_lambda, L0.A, c->M, c->G, c->GN, L0.flags,
                      c->stats);
   MGFEM_HIP_TRY(hipGetLastError());
   return MGFEM_OK;

@@ -221,7 +221,7 @@ inline unsigned nblk(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); 
 
 }  // namespace
 
-int setup_hierarchy(mgfem_ctx* c, const double* psi_in) {
+int setup_hierarchy(mgfem_ctx* c, const double* psi_in, const double* chi_in) {
   const int tb = 256;
   const int nl = (int)c->lv.size();
   const bool mixed = c->p.precision == MGFEM_PREC_MIXED;
@@ -230,7 +230,7 @@ int setup_hierarchy(mgfem_ctx* c, const double* psi_in) {
     Level& F = c->lv[l];
     Level& C = c->lv[l + 1];
     if (c->p.coarse_op == MGFEM_COARSE_REDISCRETISED) {
-      const int rc = assemble_level(c, l + 1, psi_in);
+      const int rc = assemble_level(c, l + 1, psi_in, chi_in);
       if (rc != MGFEM_OK) return rc;
       continue;
     }

@@ -207,6 +207,8 @@ struct mgfem_ctx {
   double* M = nullptr;
   double* G = nullptr;
   double* cut_rows = nullptr;  // 18 per cut-cell vertex (M row, G row), in cut-list order
+  double* GN = nullptr;        // 9 planes of the Neumann boundary mass (mixed boundaries only)
+  double* cut_rows_n = nullptr;  // 9 per cut-cell vertex: the GN row, in cut-list order
   double* F = nullptr;
   double* F64tmp = nullptr;  // outer residual / scratch on level 0
   double* zero = nullptr;    // all-zero vector of level 0
@@ -264,23 +266,24 @@ hipError_t ctx_alloc_t(mgfem_ctx* c, T** p, size_t count) {
 }
 
 // setup stages (geometry.hip, hierarchy.hip)
-int setup_geometry(mgfem_ctx* c, const double* psi_in);
-int setup_hierarchy(mgfem_ctx* c, const double* psi_in);
+int setup_geometry(mgfem_ctx* c, const double* psi_in, const double* chi_in);
+int setup_hierarchy(mgfem_ctx* c, const double* psi_in, const double* chi_in);
 // coarse level l assembled from scratch on its own grid from the fine input
 // level set (injection, snapping, classification, stabilisation, assembly):
 // fills lv[l].A, flags and cellcut (MGFEM_COARSE_REDISCRETISED)
-int assemble_level(mgfem_ctx* c, int l, const double* psi_in);
+int assemble_level(mgfem_ctx* c, int l, const double* psi_in, const double* chi_in);
 
 // solve stages (cycle.hip)
 // F = M f + G g, and its norm (max, sum of squares) as the next reduction
-void launch_rhs(mgfem_ctx* c, const double* f, const double* g, double* F);
+void launch_rhs(mgfem_ctx* c, const double* f, const double* g, const double* gN, double* F);
 // mixed outer step: u_out = u + e, r = F - A u_out, r32 = float(r), z32 = 0 on
 // the active nodes, and the norm of r as the next reduction (F = lv[0].b)
 void launch_outer(mgfem_ctx* c, const double* u, const float* e, double* u_out, float* r32, float* z32);
 // y = M x and y = G^T x on the fine grid (every node of y written)
 void launch_mass_apply(mgfem_ctx* c, const double* x, double* y);
 void launch_gt_apply(mgfem_ctx* c, const double* x, double* y);
-int build_cut_rows(mgfem_ctx* c);  // gathered M and G rows of the cut-cell vertices
+int build_cut_rows(mgfem_ctx* c);  // gathered M, G (and GN) rows of the cut-cell vertices
+void launch_gn_apply(mgfem_ctx* c, const double* x, double* y);  // y = GN x
 void launch_mask_inactive(mgfem_ctx* c, double* u);
 void launch_residual_norm(mgfem_ctx* c, const double* F, const double* u, double* r_out);
 void launch_dot_reduce(mgfem_ctx* c, const double* a, const double* b);

@@ -1,0 +1,186 @@
+"""GPU parity of mixed Dirichlet/Neumann boundaries (section 2, eqs.
+disc_bil_form and disc_rhs; section 5.3, the annulus and the leaf) through
+mgfem_setup_mixed_bc / mgfem_solve_mixed_bc / mgfem_adjoint_neumann, against
+the oracle: stencils of A, M, G and GN and lambda_K, cycle iterates, converged
+solutions, the linear solutions the discretisation reproduces exactly, the
+two-grid factors, rediscretised coarse levels, and dJ/dg_N.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint as oadj
+from oracle import assembly as oasm
+from oracle import multigrid as omg
+
+from helpers import planes_from_csr, rel_max
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_05105_amd as mg
+    return mg
+
+
+GEN = {"annulus": W.annulus_mms, "leaf": W.leaf_mms}
+
+
+@pytest.mark.parametrize("name,N", [("annulus", 128), ("leaf", 128), ("annulus", 512), ("leaf", 512)])
+def test_mixed_setup_matches_oracle(name, N):
+    mg = _gpu()
+    p = GEN[name](N)
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    s = mg.Solver(p.psi, N, chi=p.chi)
+    lam = s.export(mg._lib.EXPORT_CELL_LAMBDA).cpu().numpy()
+    assert rel_max(lam, d.cell_lambda) < 1e-12
+    cut = d.cut_cells
+    assert np.any(d.cell_lambda[cut] == 0.0) and np.any(d.cell_lambda[cut] > 0.0)
+    for what, M in ((mg._lib.EXPORT_A, d.A), (mg._lib.EXPORT_M, d.M), (mg._lib.EXPORT_G, d.G),
+                    (mg._lib.EXPORT_GN, d.GN)):
+        got = s.export(what).cpu().numpy().reshape(9, -1)
+        ref = planes_from_csr(M, N)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), what
+    fl = s.export(mg._lib.EXPORT_NODE_FLAGS).cpu().numpy().astype(int)
+    assert np.array_equal((fl & 1) == 1, d.active)
+
+
+@pytest.mark.parametrize("name", ["annulus", "leaf"])
+def test_mixed_solve_matches_oracle(name):
+    mg = _gpu()
+    N = 256
+    p = GEN[name](N)
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    H = omg.build_hierarchy(d)
+    F = d.rhs(p.f, p.g, p.gN)
+    s = mg.Solver(p.psi, N, chi=p.chi)
+    u, hist = s.solve(p.f, p.g, gN=p.gN, tol=-1.0, max_cycles=3)
+    assert rel_max(s.export(mg._lib.EXPORT_RHS).cpu().numpy(), F) < 1e-13
+    ref = omg.solve(H, F, tol=-1.0, max_cycles=3)
+    assert rel_max(u.cpu().numpy(), ref.u) < 1e-11
+    u, hist = s.solve(p.f, p.g, gN=p.gN, tol=1e-10, max_cycles=60)
+    ref = omg.solve(H, F, tol=1e-10, max_cycles=60)
+    assert s.last_status == 0 and ref.converged
+    assert len(hist) == len(ref.hist)
+    assert rel_max(u.cpu().numpy(), ref.u) < 1e-10
+    assert np.abs(hist[1:] / hist[:-1] - ref.rho).max() < 0.02
+    ug = u.cpu().numpy()
+    assert np.all(ug[~d.active] == 0)
+    # the Neumann data enter: without them the answer differs
+    u0, _ = s.solve(p.f, p.g, tol=1e-10, max_cycles=60)
+    assert rel_max(u0.cpu().numpy(), ug) > 1e-3
+
+
+@pytest.mark.parametrize("case", ["strip_x", "strip_y", "rectangle"])
+def test_linear_solution_reproduced_on_gpu(case):
+    mg = _gpu()
+    N = 128
+    p = {"strip_x": lambda: W.linear_strip(N, axis=0),
+         "strip_y": lambda: W.linear_strip(N, axis=1),
+         "rectangle": lambda: W.linear_rectangle(N)}[case]()
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    s = mg.Solver(p.psi, N, chi=p.chi)
+    u, hist = s.solve(p.f, p.g, gN=p.gN, tol=1e-13, max_cycles=80)
+    assert s.last_status == 0
+    ug = u.cpu().numpy()
+    assert np.abs(ug - p.u_exact)[d.active].max() < 1e-9
+
+
+@pytest.mark.parametrize("name", ["annulus", "leaf"])
+def test_two_grid_factor_on_gpu(name):
+    """h = 2^-5 on [-1, 1]^2, gamma = 2, eta = 4, the protocol of section 5.3."""
+    mg = _gpu()
+    N = 64
+    p = GEN[name](N)
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    s = mg.Solver(p.psi, N, chi=p.chi, cycle=mg.CYCLE_TWO_GRID)
+    n = (N + 1) ** 2
+    z = np.zeros(n)
+    _, hist = s.solve(z, z, gN=z, tol=-1.0, max_cycles=30, u0=np.ones(n))
+    rho = float(np.mean((hist[1:] / hist[:-1])[20:30]))
+    assert rho < 0.12
+    assert abs(rho - omg.rho_protocol(omg.two_grid(d), eta=4)) < 0.02
+
+
+def test_rediscretised_levels_with_neumann():
+    mg = _gpu()
+    N = 128
+    p = W.annulus_mms(N)
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    H = omg.build_hierarchy(d, rediscretise=(p.psi, {"chi": p.chi}))
+    s = mg.Solver(p.psi, N, chi=p.chi, coarse_op=mg.COARSE_REDISCRETISED)
+    for lv in range(1, s.n_levels):
+        got = s.export(mg._lib.EXPORT_A, lv).cpu().numpy().reshape(9, -1)
+        ref = planes_from_csr(H.levels[lv].A, s.level_n(lv))
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), lv
+    F = d.rhs(p.f, p.g, p.gN)
+    u, _ = s.solve(p.f, p.g, gN=p.gN, tol=-1.0, max_cycles=3)
+    ref = omg.solve(H, F, tol=-1.0, max_cycles=3)
+    assert rel_max(u.cpu().numpy(), ref.u) < 1e-11
+
+
+def test_neumann_gradient_matches_oracle():
+    mg = _gpu()
+    N = 128
+    k = 8
+    p = W.annulus_mms(N)
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    H = omg.build_hierarchy(d)
+    ut = W.adjoint_target(N)
+    s = mg.Solver(p.psi, N, chi=p.chi)
+    u, _ = s.solve(p.f, p.g, gN=p.gN, tol=-1.0, max_cycles=k)
+    J, dJdu = s.misfit(u, ut)
+    _, _, lam, _ = s.adjoint(dJdu, tol=-1.0, max_cycles=k)
+    dgn = s.neumann_gradient(lam)
+    uo = omg.solve(H, d.rhs(p.f, p.g, p.gN), tol=-1.0, max_cycles=k).u
+    _, dJduo = oadj.misfit(d, uo, ut)
+    lamo = oadj.adjoint_solve(H, dJduo, tol=-1.0, max_cycles=k).u
+    assert rel_max(dgn.cpu().numpy(), oadj.neumann_gradient(d, lamo)) < 1e-10
+    # central differences along seeded directions (J is quadratic in g_N)
+    gN0 = torch.tensor(p.gN, device="cuda:0")
+    utd = torch.tensor(ut, device="cuda:0")
+    eps = 1e-4
+    for q, dv in enumerate(W.random_directions(d.n, 4, seed=2)):
+        dvt = torch.tensor(dv, device="cuda:0")
+
+        def J_at(gn):
+            uu, _ = s.solve(p.f, p.g, gN=gn, tol=-1.0, max_cycles=k)
+            return s.misfit(uu, utd)[0]
+
+        fd = (J_at(gN0 + eps * dvt) - J_at(gN0 - eps * dvt)) / (2 * eps)
+        assert float(dgn @ dvt) == pytest.approx(fd, rel=1e-6, abs=50 * 2.2e-16 * abs(J) / eps), q
+
+
+def test_mixed_precision_with_neumann():
+    mg = _gpu()
+    N = 512
+    p = W.leaf_mms(N)
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    F = d.rhs(p.f, p.g, p.gN)
+    tight = omg.solve(omg.build_hierarchy(d), F, tol=1e-14, max_cycles=80)
+    s64 = mg.Solver(p.psi, N, chi=p.chi)
+    u64, _ = s64.solve(p.f, p.g, gN=p.gN, tol=1e-10)
+    err64 = rel_max(u64.cpu().numpy(), tight.u)
+    s = mg.Solver(p.psi, N, chi=p.chi, precision=mg.PREC_MIXED)
+    u, hist = s.solve(p.f, p.g, gN=p.gN, tol=1e-10)
+    assert s.last_status == 0 and hist[-1] <= 1e-10 * np.abs(F).max()
+    err = rel_max(u.cpu().numpy(), tight.u)
+    assert err < 10 * err64 + 1e-13, (err, err64)
+
+
+def test_handles_without_indicator_ignore_neumann_data():
+    mg = _gpu()
+    N = 128
+    p = W.annulus_mms(N)
+    s = mg.Solver(p.psi, N)
+    u1, h1 = s.solve(p.f, p.g, tol=1e-10)
+    u2, h2 = s.solve(p.f, p.g, gN=p.gN, tol=1e-10)
+    assert torch.equal(u1, u2) and np.array_equal(h1, h2)
+    assert float(s.export(mg._lib.EXPORT_GN).abs().max()) == 0.0
+    # an indicator that is negative everywhere gives the Dirichlet problem
+    sd = mg.Solver(p.psi, N, chi=-np.ones(s.n))
+    u3, h3 = sd.solve(p.f, p.g, gN=p.gN, tol=1e-10)
+    assert torch.equal(u1, u3) and np.array_equal(h1, h3)
