@@ -14,7 +14,9 @@ Q1 shape functions and
     S_ij = int_{K cap Omega} grad phi_i . grad phi_j      M_ij = int_{K cap Omega} phi_i phi_j
     B_ij = int_{K cap Gamma} (n . grad phi_j) phi_i       L_ij = int_{K cap Gamma} phi_i phi_j
 
-the element matrix is A_K = S - B - B^T + lambda_K L.  The data f and g enter
+the element matrix is A_K = S - B - B^T + lambda_K L.  With the global rule
+of section 5.2 one lambda = gamma C serves every cut cell, C the largest
+eigenvalue of the global pencil (global_eigen_constant).  The data f and g enter
 through their nodal Q1 interpolants (a reading: the paper writes exact
 integrals of f and g), so that F = M f + G g with G_K = lambda_K L - B^T,
 i.e. G_ij = int lambda_K phi_i phi_j - (n . grad phi_i) phi_j.
@@ -187,6 +189,61 @@ class Discretisation:
         return np.nonzero((t != geo.EXTERNAL) & (t != geo.INTERNAL))[0]
 
 
+def global_pencil(psi4, ctype, N, h, chi4=None):
+    """The matrices of the global generalised eigenproblem of section 5.2 on
+    the full node grid: K_ij = int_{Gamma_D} (n.grad phi_i)(n.grad phi_j)
+    (physical K = K_ref / h) and S_ij = int_Omega grad phi_i . grad phi_j,
+    with the boolean mask of the active nodes."""
+    V = cell_vertex_indices(N)
+    n = (N + 1) ** 2
+    S_int, _ = interior_matrices(h)
+    rows, cols, sval, kval = [], [], [], []
+    inner = np.nonzero(ctype == geo.INTERNAL)[0]
+    Vi = V[inner]
+    rows.append(np.repeat(Vi[:, :, None], 4, axis=2).ravel())
+    cols.append(np.repeat(Vi[:, None, :], 4, axis=1).ravel())
+    sval.append(np.broadcast_to(S_int, (len(inner), 4, 4)).ravel())
+    kval.append(np.zeros(len(inner) * 16))
+    for c in np.nonzero((ctype != geo.EXTERNAL) & (ctype != geo.INTERNAL))[0]:
+        _, polys, segs, _ = geo.cut_geometry(psi4[c])
+        dseg, _ = split_segments(segs, None if chi4 is None else chi4[c])
+        S, _, _, _, Kn = reference_integrals(polys, dseg)
+        v = V[c]
+        rows.append(np.repeat(v, 4))
+        cols.append(np.tile(v, 4))
+        sval.append(S.ravel())
+        kval.append((Kn / h).ravel())
+    r = np.concatenate(rows)
+    c_ = np.concatenate(cols)
+    S = sp.coo_matrix((np.concatenate(sval), (r, c_)), shape=(n, n)).tocsr()
+    K = sp.coo_matrix((np.concatenate(kval), (r, c_)), shape=(n, n)).tocsr()
+    act = np.zeros(n, dtype=bool)
+    act[V[ctype != geo.EXTERNAL].ravel()] = True
+    return K, S, act
+
+
+def global_eigen_constant(psi4, ctype, N, h, chi4=None):
+    """C of the global generalised eigenproblem of section 5.2: the largest
+    Lambda with K v = Lambda S v over the active nodes (global_pencil).
+
+    Both matrices vanish on the constants, and the Rayleigh quotient
+    v^T K v / v^T S v does not change when a constant is added to v, so the
+    eigenvalues are taken on the complement of the constants (the rank sense
+    of section 4.4) by fixing v = 0 at one active node; for a connected active
+    domain S is then positive definite."""
+    K, S, act = global_pencil(psi4, ctype, N, h, chi4)
+    idx = np.nonzero(act)[0][1:]  # fix v = 0 at the first active node
+    S = S[idx][:, idx]
+    K = K[idx][:, idx]
+    S = 0.5 * (S + S.T)
+    K = 0.5 * (K + K.T)
+    if len(idx) <= 4000:
+        return float(scipy.linalg.eigh(K.toarray(), S.toarray(), eigvals_only=True).max())
+    import scipy.sparse.linalg as spla
+    return float(spla.eigsh(K.tocsc(), k=1, M=S.tocsc(), which="LA", tol=1e-14,
+                            return_eigenvectors=False)[0])
+
+
 def cell_vertex_indices(N):
     """(N*N, 4) global node indices of v0..v3 of every cell."""
     ci, cj = np.meshgrid(np.arange(N), np.arange(N), indexing="xy")
@@ -206,6 +263,11 @@ def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
     n = (N + 1) ** 2
 
     chi4 = None if chi is None else geo.cell_vertex_values(np.asarray(chi, dtype=np.float64), N)
+    C_global = None
+    if rule == geo.STAB_GLOBAL:
+        # one lambda = gamma C for every cut cell (section 5.2)
+        C_global = global_eigen_constant(psi4, ctype, N, h, chi4)
+        rule, lambda_fixed = geo.STAB_FIXED, gamma * C_global
     rows, cols, aval, mval, gval, nval = [], [], [], [], [], []
     S_int, M_int = interior_matrices(h)
     inner = np.nonzero(ctype == geo.INTERNAL)[0]
@@ -225,7 +287,7 @@ def assemble(psi, N, box=(-1.0, -1.0, 1.0, 1.0), gamma=2.0, alpha=1.75,
         A_K, M_K, G_K, N_K, (_, C, lam) = cut_element(
             psi4[c], h, gamma, rule, lambda_fixed, None if chi4 is None else chi4[c])
         cell_lambda[c] = lam
-        cell_C[c] = C
+        cell_C[c] = C if C_global is None else C_global
         v = V[c]
         rows.append(np.repeat(v, 4))
         cols.append(np.tile(v, 4))

@@ -25,7 +25,7 @@ EXTERNAL, TRIANGLE, QUAD, PENTAGON, INTERNAL, SADDLE_SPLIT, SADDLE_HEX = range(7
 
 REF_VERTS = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
 
-STAB_PAPER, STAB_LOCAL_EIG, STAB_FIXED = 0, 1, 2
+STAB_PAPER, STAB_LOCAL_EIG, STAB_FIXED, STAB_GLOBAL = 0, 1, 2, 3
 
 
 # ----------------------------------------------------------------------------
