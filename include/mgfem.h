@@ -61,7 +61,13 @@ enum mgfem_stab {
                                formula, eq. c_pentagon for pentagons */
   MGFEM_STAB_LOCAL_EIG = 1, /* max eigenvalue of the local 4x4 generalised
                                eigenproblem of section 5.2 */
-  MGFEM_STAB_FIXED = 2      /* lambda_K = lambda_fixed on every cut cell */
+  MGFEM_STAB_FIXED = 2,     /* lambda_K = lambda_fixed on every cut cell */
+  MGFEM_STAB_GLOBAL = 3     /* one lambda = gamma C on every cut cell, C the largest
+                               eigenvalue of the global generalised eigenproblem
+                               K v = Lambda S v of section 5.2 (K over Gamma_D, S the
+                               stiffness over Omega), found at setup by Lanczos
+                               iterations with multigrid solves for S; not with
+                               MGFEM_COARSE_REDISCRETISED */
 };
 
 enum mgfem_precision {
@@ -119,6 +125,8 @@ typedef struct {
   double min_theta;          /* smallest cut fraction on a cut edge */
   double max_lambda;         /* largest lambda_K */
   double setup_ms;           /* device time of the last setup */
+  double global_C;           /* MGFEM_STAB_GLOBAL: C of the global eigenproblem, else 0 */
+  int32_t global_iters;      /* MGFEM_STAB_GLOBAL: Lanczos steps taken, else 0 */
 } mgfem_info;
 
 /* Fill *p with the defaults listed above. */

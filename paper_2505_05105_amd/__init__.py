@@ -19,7 +19,7 @@ import torch
 
 from . import _lib
 from ._lib import (COARSE_GALERKIN, COARSE_REDISCRETISED, CYCLE_TWO_GRID, CYCLE_V, CYCLE_W,  # noqa: F401
-                   PREC_FP64, PREC_MIXED, STAB_FIXED, STAB_LOCAL_EIG, STAB_PAPER, MgfemError,
+                   PREC_FP64, PREC_MIXED, STAB_FIXED, STAB_GLOBAL, STAB_LOCAL_EIG, STAB_PAPER, MgfemError,
                    default_params)
 
 __all__ = ["Solver", "BatchedSolver", "GhostFEMSolve", "MgfemError", "default_params"]

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmgfem.so")
 
 OK, ERR_INVALID_ARG, ERR_OOM, ERR_HIP, ERR_NOT_CONVERGED, ERR_DIVERGED, \
     ERR_SINGULAR_COARSE, ERR_EMPTY_DOMAIN, ERR_UNSUPPORTED = range(9)
-STAB_PAPER, STAB_LOCAL_EIG, STAB_FIXED = 0, 1, 2
+STAB_PAPER, STAB_LOCAL_EIG, STAB_FIXED, STAB_GLOBAL = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 CYCLE_V, CYCLE_W, CYCLE_TWO_GRID = 1, 2, 3
 COARSE_GALERKIN, COARSE_REDISCRETISED = 0, 1
@@ -46,7 +46,8 @@ class Info(C.Structure):
         ("N", C.c_int32), ("n_levels", C.c_int32), ("n_active", C.c_int64),
         ("n_cells_by_type", C.c_int64 * 7), ("n_snapped", C.c_int64),
         ("n_cut_vertices", C.c_int64), ("coarse_n", C.c_int32), ("min_theta", C.c_double),
-        ("max_lambda", C.c_double), ("setup_ms", C.c_double),
+        ("max_lambda", C.c_double), ("setup_ms", C.c_double), ("global_C", C.c_double),
+        ("global_iters", C.c_int32),
     ]
 
 

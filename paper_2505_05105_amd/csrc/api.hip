@@ -25,7 +25,9 @@ int fail(mgfem_ctx* c, int code, const std::string& msg) {
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 int check_params(const mgfem_params& p, int N, std::string& why) {
-  if (p.stab_rule < 0 || p.stab_rule > 2) return why = "stab_rule", 1;
+  if (p.stab_rule < 0 || p.stab_rule > 3) return why = "stab_rule", 1;
+  if (p.stab_rule == MGFEM_STAB_GLOBAL && p.coarse_op == MGFEM_COARSE_REDISCRETISED)
+    return why = "the global stabilisation rule needs Galerkin coarse operators", 1;
   if (p.stab_rule != MGFEM_STAB_FIXED && !(p.gamma > 1.0))
     return why = "gamma must exceed 1 (coercivity, section 4.4)", 1;
   if (p.stab_rule == MGFEM_STAB_FIXED && !(p.lambda_fixed > 0.0)) return why = "lambda_fixed", 1;
@@ -225,8 +227,11 @@ const char* mgfem_last_error(mgfem_handle h) {
 
 namespace {
 
+int global_constant(const double* psi, const double* chi, int32_t N, const mgfem_params& p, void* stream,
+                    double* C_out, int* iters_out);
+
 int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mgfem_params* pin, void* stream,
-               mgfem_handle* out) {
+               mgfem_handle* out, int op_kind = kOpAssembled) {
   if (!out) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!psi_dev) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "psi_dev is NULL");
@@ -235,9 +240,18 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
   else mgfem_default_params(&p);
   std::string why;
   if (check_params(p, N, why)) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "invalid parameter: " + why);
+  double C_global = 0.0;
+  int global_iters = 0;
+  if (p.stab_rule == MGFEM_STAB_GLOBAL && op_kind == kOpAssembled) {
+    const int rc = global_constant(psi_dev, chi_dev, N, p, stream, &C_global, &global_iters);
+    if (rc != MGFEM_OK) return rc;  // the message is already set
+  }
   mgfem_ctx* c = new (std::nothrow) mgfem_ctx();
   if (!c) return fail(nullptr, MGFEM_ERR_OOM, "host allocation failed");
   c->p = p;
+  c->op_kind = op_kind;
+  c->C_global = C_global;
+  c->lambda_global = p.gamma * C_global;
   c->s = reinterpret_cast<hipStream_t>(stream);
   c->N = N;
   c->h = (p.x_hi - p.x_lo) / N;
@@ -336,6 +350,8 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
   I.min_theta = std::isinf(mt) ? 0.0 : mt;
   I.max_lambda = ml;
   I.setup_ms = ms;
+  I.global_C = C_global;
+  I.global_iters = global_iters;
 #undef SETUP_TRY
   *out = c;
   return MGFEM_OK;
@@ -623,6 +639,144 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     c->last_error = "tolerance not reached within max_cycles";
     return MGFEM_ERR_NOT_CONVERGED;
   }
+  return MGFEM_OK;
+}
+
+// Largest eigenvalue and the last component of its unit eigenvector for the
+// symmetric tridiagonal matrix with diagonal a and off-diagonal b: bisection
+// on the Sturm count, then two steps of inverse iteration with the factorised
+// (theta' I - T), positive definite for theta' just above the top eigenvalue.
+void top_ritz(const std::vector<double>& a, const std::vector<double>& b, double& theta, double& ylast) {
+  const int m = (int)a.size();
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_above = [&](double x) {  // eigenvalues > x
+    int cnt = 0;
+    double d = 1.0;
+    for (int i = 0; i < m; ++i) {
+      d = (a[i] - x) - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d > 0.0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(hi), std::fabs(lo)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_above(mid) >= 1) lo = mid;
+    else hi = mid;
+  }
+  theta = hi;
+  const double sh = hi + 1e-13 * std::max(1.0, std::fabs(hi));
+  std::vector<double> dg(m), y(m, 1.0);
+  for (int rep = 0; rep < 2; ++rep) {
+    // (sh I - T) z = y by the L D L^T recurrence of a tridiagonal matrix
+    std::vector<double> l(m, 0.0), z(m);
+    dg[0] = sh - a[0];
+    for (int i = 1; i < m; ++i) {
+      l[i] = -b[i - 1] / dg[i - 1];
+      dg[i] = (sh - a[i]) - l[i] * (-b[i - 1]);
+    }
+    z[0] = y[0];
+    for (int i = 1; i < m; ++i) z[i] = y[i] - l[i] * z[i - 1];
+    for (int i = 0; i < m; ++i) z[i] /= dg[i];
+    for (int i = m - 2; i >= 0; --i) z[i] -= l[i + 1] * z[i + 1];
+    double nrm = 0.0;
+    for (int i = 0; i < m; ++i) nrm += z[i] * z[i];
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < m; ++i) y[i] = z[i] / nrm;
+  }
+  ylast = y[m - 1];
+}
+
+// C of the global generalised eigenproblem K v = Lambda S v (section 5.2) by
+// the Lanczos iteration for S^-1 K in the S inner product.  S is the cut
+// stiffness of a second context (kOpStiffness) whose multigrid solves give
+// S^-1; K (over the Dirichlet segments) is applied from its gathered rows.
+// Both vanish on the constants, so every iterate is kept free of them (mean
+// over the active nodes removed); the diagonal scaling of the stored rows of
+// S by 1 + 1e-12 that keeps the coarsest factor positive changes C by a
+// relative 1e-12 times the ratio of the diagonal to the quadratic form of S
+// on the top eigenvector.  Stops when the Ritz residual of the top Ritz value
+// falls below 1e-11 of it, or after 400 steps.
+int global_constant(const double* psi, const double* chi, int32_t N, const mgfem_params& p, void* stream,
+                    double* C_out, int* iters_out) {
+  mgfem_params ps = p;
+  ps.stab_rule = MGFEM_STAB_FIXED;
+  ps.lambda_fixed = 1.0;
+  ps.precision = MGFEM_PREC_FP64;
+  ps.cycle = MGFEM_CYCLE_V;
+  ps.coarse_op = MGFEM_COARSE_GALERKIN;
+  mgfem_ctx* s = nullptr;
+  int rc = setup_impl(psi, chi, N, &ps, stream, &s, kOpStiffness);
+  if (rc != MGFEM_OK) return fail(nullptr, rc, "global stabilisation: " + g_setup_error);
+  struct Owner {
+    mgfem_ctx* s;
+    ~Owner() { free_ctx(s); }
+  } owner{s};
+  auto bail = [&](int code) { return fail(nullptr, code, "global stabilisation: " + s->last_error); };
+  const int64_t n = s->lv[0].n;
+  double *q = nullptr, *qp = nullptr, *w = nullptr, *u = nullptr, *sw = nullptr, *ones = nullptr;
+  for (double** v : {&q, &qp, &w, &u, &sw, &ones})
+    if (ctx_alloc_t(s, v, n) != hipSuccess) return fail(nullptr, MGFEM_ERR_OOM, "global stabilisation: allocation");
+  launch_active_ones(s, ones);
+  const double nact = (double)s->info.n_active;
+  auto dot = [&](const double* x, const double* y, double& out) {
+    launch_dot_reduce(s, x, y);
+    double mx, l2;
+    return read_norm(s, mx, l2, &out);
+  };
+  auto project = [&](double* x) {  // remove the mean over the active nodes
+    double sum = 0.0;
+    const int r = dot(x, ones, sum);
+    if (r == MGFEM_OK) launch_shift_active(s, x, sum / nact);
+    return r;
+  };
+  auto snorm2 = [&](const double* x, double& out) {  // x^T S x (sw = -S x)
+    launch_residual_norm(s, s->zero, x, sw);
+    double t = 0.0;
+    const int r = dot(x, sw, t);
+    out = -t;
+    return r;
+  };
+  launch_start_vector(s, w);
+  if ((rc = project(w)) || (rc = snorm2(w, *C_out))) return bail(rc);
+  double nn = *C_out;
+  *C_out = 0.0;
+  *iters_out = 0;
+  if (!(nn > 0.0)) return MGFEM_OK;
+  launch_scale(s, q, w, 1.0 / std::sqrt(nn));
+  launch_zero(s, qp, n);
+  std::vector<double> al, be, hist(61);
+  double beta = 0.0, theta = 0.0, ylast = 1.0;
+  const int max_steps = (int)std::min<int64_t>(400, s->info.n_active);
+  for (int j = 0; j < max_steps; ++j) {
+    double a = 0.0;
+    launch_k_apply(s, q, u);  // u = K q
+    if ((rc = dot(q, u, a))) return bail(rc);
+    launch_copy(s, s->F, u, n);
+    int nc = 0;
+    rc = iterate(s, w, s->F, 1e-12, 60, false, false, false, -1.0, hist.data(), &nc);  // w = S^-1 u
+    if (rc != MGFEM_OK && !(nc > 0 && hist[nc] <= 1e-10 * hist[0])) return bail(rc);
+    if ((rc = project(w))) return bail(rc);
+    launch_lanczos_update(s, w, q, qp, a, beta);
+    double bb = 0.0;
+    if ((rc = snorm2(w, bb))) return bail(rc);
+    al.push_back(a);
+    top_ritz(al, be, theta, ylast);
+    beta = std::sqrt(std::max(bb, 0.0));
+    *iters_out = j + 1;
+    if (beta * std::fabs(ylast) <= 1e-11 * std::fabs(theta) || beta <= 1e-14 * std::fabs(theta)) break;
+    be.push_back(beta);
+    std::swap(qp, q);
+    launch_scale(s, q, w, 1.0 / beta);
+  }
+  *C_out = theta;
+  hipError_t e = hipStreamSynchronize(s->s);
+  if (e != hipSuccess) return fail(nullptr, MGFEM_ERR_HIP, "global stabilisation: stream error");
   return MGFEM_OK;
 }
 

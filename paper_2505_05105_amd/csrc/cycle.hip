@@ -451,8 +451,9 @@ void launch_outer(mgfem_ctx* c, const double* u, const float* e, double* u_out, 
 namespace {
 // the M and G rows (and GN rows) of every cut-cell vertex of level 0, in cut-list order
 __global__ void k_gather_cut_rows(const int* __restrict__ cut_list, int ncut, const double* __restrict__ M,
-                                  const double* __restrict__ G, const double* __restrict__ GN, int64_t n,
-                                  double* __restrict__ rows, double* __restrict__ rows_n) {
+                                  const double* __restrict__ G, const double* __restrict__ GN,
+                                  const double* __restrict__ Kp, int64_t n, double* __restrict__ rows,
+                                  double* __restrict__ rows_n, double* __restrict__ rows_k) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= ncut) return;
   const int64_t k = cut_list[t];
@@ -460,6 +461,7 @@ __global__ void k_gather_cut_rows(const int* __restrict__ cut_list, int ncut, co
     rows[18 * (int64_t)t + p] = M[p * n + k];
     rows[18 * (int64_t)t + 9 + p] = G[p * n + k];
     if (GN) rows_n[9 * (int64_t)t + p] = GN[p * n + k];
+    if (Kp) rows_k[9 * (int64_t)t + p] = Kp[p * n + k];
   }
 }
 }  // namespace
@@ -469,9 +471,11 @@ int build_cut_rows(mgfem_ctx* c) {
   const int ncut = L.cut_off[4];
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cut_rows, 18 * (size_t)std::max(1, ncut)));
   if (c->GN) MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cut_rows_n, 9 * (size_t)std::max(1, ncut)));
+  if (c->Kp) MGFEM_HIP_TRY(ctx_alloc_t(c, &c->cut_rows_k, 9 * (size_t)std::max(1, ncut)));
   if (ncut > 0)
     hipLaunchKernelGGL(k_gather_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->M, c->G,
-                       (const double*)c->GN, L.n, c->cut_rows, c->cut_rows_n);
+                       (const double*)c->GN, (const double*)c->Kp, L.n, c->cut_rows, c->cut_rows_n,
+                       c->cut_rows_k);
   MGFEM_HIP_TRY(hipGetLastError());
   return MGFEM_OK;
 }
@@ -486,6 +490,15 @@ void launch_mass_apply(mgfem_ctx* c, const double* x, double* y) {
   if (ncut > 0)
     hipLaunchKernelGGL(k_cut_rows, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut, c->cut_rows, x,
                        (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, y, N);
+}
+
+void launch_k_apply(mgfem_ctx* c, const double* x, double* y) {
+  const Level& L = c->lv[0];
+  launch_zero(c, y, L.n);
+  const int ncut = L.cut_off[4];
+  if (c->Kp && ncut > 0)
+    hipLaunchKernelGGL(k_cut_rows9, dim3(nblk(ncut, 256)), dim3(256), 0, c->s, L.cut_list, ncut,
+                       (const double*)c->cut_rows_k, x, y, c->N);
 }
 
 void launch_gn_apply(mgfem_ctx* c, const double* x, double* y) {

@@ -488,11 +488,14 @@ __constant__ int kVx[4] = {0, 1, 1, 0};
 __constant__ int kVy[4] = {0, 0, 1, 1};
 
 // Gather the rows of A, M, G of every node from its (up to) four cells.
+// With stiffness_only (the operator of the global eigenproblem) A receives the
+// cut stiffness S alone, its stored rows with the diagonal scaled by
+// 1 + diag_shift, and Kp the boundary normal-derivative matrix K = Kn / h.
 __global__ void k_assemble(const double* __restrict__ psi, const double* __restrict__ chi, int N,
                            mgfem_params p, double h, const uint8_t* __restrict__ ctype,
                            const double* __restrict__ clam, double* __restrict__ A, double* __restrict__ Mm,
                            double* __restrict__ G, double* __restrict__ GN, uint8_t* __restrict__ flags,
-                           Stats* st) {
+                           Stats* st, int stiffness_only, double diag_shift, double* __restrict__ Kp) {
   __shared__ unsigned int nact;
   if (threadIdx.x == 0) nact = 0;
   __syncthreads();
@@ -501,8 +504,8 @@ __global__ void k_assemble(const double* __restrict__ psi, const double* __restr
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k < n) {
     int i = (int)(k % stride), j = (int)(k / stride);
-    double a[9], m[9], g[9], gn[9];
-    for (int q = 0; q < 9; ++q) a[q] = m[q] = g[q] = gn[q] = 0.0;
+    double a[9], m[9], g[9], gn[9], kn[9];
+    for (int q = 0; q < 9; ++q) a[q] = m[q] = g[q] = gn[q] = kn[q] = 0.0;
     bool active = false, regular = true;
     // cells around the node, with the node's local vertex number in each
     const int cdx[4] = {-1, 0, 0, -1}, cdy[4] = {-1, -1, 0, 0}, loc[4] = {2, 3, 0, 1};
@@ -544,9 +547,14 @@ __global__ void k_assemble(const double* __restrict__ psi, const double* __restr
           int dxo = ci + kVx[mm] - i, dyo = cj + kVy[mm] - j;
           int pl = (dxo + 1) + 3 * (dyo + 1);
           // A_K = S - B - B^T + lambda L with the symmetric pair summed first
-          double sl = I.S[lv][mm] + lh * I.L[lv][mm];
-          double nit = I.B[lv][mm] + I.B[mm][lv];
-          a[pl] += sl - nit;
+          if (stiffness_only) {
+            a[pl] += I.S[lv][mm];
+            kn[pl] += I.Kn[lv][mm] / h;
+          } else {
+            double sl = I.S[lv][mm] + lh * I.L[lv][mm];
+            double nit = I.B[lv][mm] + I.B[mm][lv];
+            a[pl] += sl - nit;
+          }
           m[pl] += (h * h) * I.Mm[lv][mm];
           // G_ij = lambda L_ij - int (n . grad phi_i) phi_j
           g[pl] += lh * I.L[lv][mm] - I.B[mm][lv];
@@ -554,8 +562,10 @@ __global__ void k_assemble(const double* __restrict__ psi, const double* __restr
         }
       }
     }
+    if (stiffness_only && active && !regular) a[4] *= 1.0 + diag_shift;
     for (int q = 0; q < 9; ++q) {
       A[q * n + k] = a[q];
+      if (Kp) Kp[q * n + k] = kn[q];
       if (Mm) Mm[q * n + k] = m[q];  // mass and boundary load: finest level only
       if (G) G[q * n + k] = g[q];
       if (GN) GN[q * n + k] = gn[q];
@@ -615,13 +625,20 @@ int assemble_level(mgfem_ctx* c, int l, const double* psi_in, const double* chi_
                      (const double*)chi, N, c->p, h, ct, lam, L.cellcut, st);
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, (const double*)psi,
                      (const double*)chi, N, c->p, h, (const uint8_t*)ct, (const double*)lam, L.A, (double*)nullptr,
-                     (double*)nullptr, (double*)nullptr, L.flags, st);
+                     (double*)nullptr, (double*)nullptr, L.flags, st, 0, 0.0, (double*)nullptr);
   MGFEM_HIP_TRY(hipGetLastError());
   return MGFEM_OK;
 }
 
 int setup_geometry(mgfem_ctx* c, const double* psi_in, const double* chi_in) {
   const int N = c->N;
+  // the global rule: one lambda for every cut cell, computed beforehand
+  mgfem_params pk = c->p;
+  if (pk.stab_rule == MGFEM_STAB_GLOBAL) {
+    pk.stab_rule = MGFEM_STAB_FIXED;
+    pk.lambda_fixed = c->lambda_global;
+  }
+  const bool stiff = c->op_kind == kOpStiffness;
   const int64_t n = (int64_t)(N + 1) * (N + 1), nc = (int64_t)N * N;
   Level& L0 = c->lv[0];
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->psi, n));
@@ -630,6 +647,7 @@ int setup_geometry(mgfem_ctx* c, const double* psi_in, const double* chi_in) {
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->M, 9 * n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &c->G, 9 * n));
   if (chi_in) MGFEM_HIP_TRY(ctx_alloc_t(c, &c->GN, 9 * n));
+  if (stiff) MGFEM_HIP_TRY(ctx_alloc_t(c, &c->Kp, 9 * n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &L0.A, 9 * n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &L0.flags, n));
   MGFEM_HIP_TRY(ctx_alloc_t(c, &L0.cellcut, nc));
@@ -638,10 +656,10 @@ int setup_geometry(mgfem_ctx* c, const double* psi_in, const double* chi_in) {
   hipLaunchKernelGGL(k_snap, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, psi_in, c->psi,
                      n, thr, c->stats);
   hipLaunchKernelGGL(k_classify, dim3((unsigned)((nc + tb - 1) / tb)), dim3(tb), 0, c->s, c->psi, chi_in, N,
-                     c->p, c->h, c->cell_type, c->cell_lambda, L0.cellcut, c->stats);
+                     pk, c->h, c->cell_type, c->cell_lambda, L0.cellcut, c->stats);
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)((n + tb - 1) / tb)), dim3(tb), 0, c->s, c->psi, chi_in, N,
-                     c->p, c->h, c->cell_type, c->cell_lambda, L0.A, c->M, c->G, c->GN, L0.flags,
-                     c->stats);
+                     pk, c->h, c->cell_type, c->cell_lambda, L0.A, c->M, c->G, c->GN, L0.flags,
+                     c->stats, stiff ? 1 : 0, stiff ? kStiffnessShift : 0.0, c->Kp);
   MGFEM_HIP_TRY(hipGetLastError());
   return MGFEM_OK;
 }

@@ -30,6 +30,12 @@ namespace mgfem {
 constexpr int kFlagActive = 1;
 constexpr int kFlagStored = 2;
 constexpr int kFlagCut = 4;
+// level-0 operator of a context: the assembled ghost-FEM matrix A, or the cut
+// stiffness S of the global eigenproblem (section 5.2), whose stored rows get
+// their diagonal scaled by 1 + kStiffnessShift so that the coarsest Cholesky
+// factor exists (S alone vanishes on the constants)
+constexpr int kOpAssembled = 0, kOpStiffness = 1;
+constexpr double kStiffnessShift = 1e-12;
 
 // cell type codes
 constexpr int kExternal = 0, kTriangle = 1, kQuad = 2, kPentagon = 3, kInternal = 4,
@@ -209,6 +215,11 @@ struct mgfem_ctx {
   double* cut_rows = nullptr;  // 18 per cut-cell vertex (M row, G row), in cut-list order
   double* GN = nullptr;        // 9 planes of the Neumann boundary mass (mixed boundaries only)
   double* cut_rows_n = nullptr;  // 9 per cut-cell vertex: the GN row, in cut-list order
+  int op_kind = 0;               // kOpAssembled or kOpStiffness
+  double* Kp = nullptr;          // kOpStiffness: 9 planes of K = int_{Gamma_D} (n.grad phi_i)(n.grad phi_j)
+  double* cut_rows_k = nullptr;  // kOpStiffness: the K rows of the cut-cell vertices
+  double lambda_global = 0.0;    // MGFEM_STAB_GLOBAL: gamma C
+  double C_global = 0.0;         // MGFEM_STAB_GLOBAL: C
   double* F = nullptr;
   double* F64tmp = nullptr;  // outer residual / scratch on level 0
   double* zero = nullptr;    // all-zero vector of level 0
@@ -284,6 +295,14 @@ void launch_mass_apply(mgfem_ctx* c, const double* x, double* y);
 void launch_gt_apply(mgfem_ctx* c, const double* x, double* y);
 int build_cut_rows(mgfem_ctx* c);  // gathered M, G (and GN) rows of the cut-cell vertices
 void launch_gn_apply(mgfem_ctx* c, const double* x, double* y);  // y = GN x
+void launch_k_apply(mgfem_ctx* c, const double* x, double* y);   // y = K x (kOpStiffness)
+// vector kernels of the global eigenproblem's Lanczos iteration (stabilise.hip)
+void launch_start_vector(mgfem_ctx* c, double* x);                  // seeded values on the active nodes
+void launch_active_ones(mgfem_ctx* c, double* x);                   // 1 on the active nodes, 0 elsewhere
+void launch_lanczos_update(mgfem_ctx* c, double* w, const double* q, const double* qp, double a, double b);
+void launch_shift_active(mgfem_ctx* c, double* w, double v);         // w -= v on the active nodes
+void launch_scale(mgfem_ctx* c, double* dst, const double* src, double s);
+void launch_axpy(mgfem_ctx* c, double* y, const double* x, double a);
 void launch_mask_inactive(mgfem_ctx* c, double* u);
 void launch_residual_norm(mgfem_ctx* c, const double* F, const double* u, double* r_out);
 void launch_dot_reduce(mgfem_ctx* c, const double* a, const double* b);
