@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fine-grid DOF/s to 1e-10 rel. residual at N=4096 (FP64 vs mixed); HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-SWEEP_KERNEL = "k_sweep<double, 64, 64, 512>"
+SWEEP_KERNEL = "k_sweep<double, 64, 32, 512>"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
 
 

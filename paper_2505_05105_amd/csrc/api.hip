@@ -299,7 +299,7 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
   SETUP_TRY(ctx_alloc_t(c, &c->red_seq_dev, 1));
   SETUP_TRY(ctx_alloc_t(c, &c->sweep_counter, 1));
   {
-    // one partial pair per level-0 sweep tile (64 x 32 tiles, or 32 x 16 below N = 1024)
+    // one partial pair per level-0 sweep tile (every tile shape holds at least 16 x 16 nodes)
     const int64_t tiles = (int64_t)(N / 16 + 2) * (N / 16 + 2);
     SETUP_TRY(ctx_alloc_t(c, &c->sweep_part, 2 * tiles));
   }

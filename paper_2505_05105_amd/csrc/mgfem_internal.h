@@ -111,6 +111,9 @@ struct Level {
   double* tp_coef = nullptr;
   float* tp_coef32 = nullptr;
   int* tc_off = nullptr;  // ntiles + 1
+  // per list entry: tile, first stored row, stored rows, first cut vertex, cut
+  // vertices (and 3 unused): one 32-byte scalar load gives a sweep tile all of it
+  int* tmeta = nullptr;
   int* tc_idx = nullptr;
   int* tc_pos = nullptr;
   int tp_max = 0, tc_max = 0;
@@ -329,13 +332,14 @@ void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32);
 void gather_snap(mgfem_ctx* c, int l, bool fp32);
 int build_plans(mgfem_ctx* c);  // cut groups and the coarse single-workgroup layout
 int build_tile_lists(mgfem_ctx* c);
-// sweep tile shapes: 64 x 64 (512 threads) on a large finest level of a
-// float64 solver (64 x 32 for the float sweeps of a mixed-precision one), 64 x 32
-// on levels with N >= 1024, 32 x 16 below
+// sweep tile shapes, all with 512 threads (a workgroup's load phase is bound
+// by the memory instructions each wave issues, so more waves per tile start
+// the phases sooner): 64 x 32 on a finest level with N >= 2048, 64 x 16 on
+// the other levels with N >= 1024, 16 x 16 below (measured on MI355X)
 constexpr int kShapeFinest = 0, kShapeLarge = 1, kShapeSmall = 2;
 inline int sweep_shape(const mgfem_ctx* c, int l) {
   const int N = c->lv[l].N;
-  if (l == 0 && N >= 2048) return c->p.precision == MGFEM_PREC_MIXED ? kShapeLarge : kShapeFinest;
+  if (l == 0 && N >= 2048) return kShapeFinest;
   return N >= 1024 ? kShapeLarge : kShapeSmall;
 }
 void set_kernel_attributes();

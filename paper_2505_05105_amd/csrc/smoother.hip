@@ -62,6 +62,7 @@ struct SweepArgs {
   const T* xc;  // coarse iterate to prolongate into the staged tile, or null
   int sc;
   // tile plan (see Level): stored rows and core cut vertices of each tile
+  const int* tmeta;
   const int* tp_off;
   const int* tp_idx;
   const T* tp_coef;
@@ -180,7 +181,9 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
   const int t = xcd * a.per + loc;
   if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
-  const int tile = a.tiles ? a.tiles[t] : t;
+  // tile, plan offsets and counts in one uniform 32-byte load
+  const int* mt = a.tmeta + 8 * t;
+  const int tile = mt[0], p0 = mt[1], nrow = mt[2], c0 = mt[3], ncut = mt[4];
   const int tx = tile % a.ntx, ty = tile / a.ntx;
   const int ox = a.i0 + tx * TW - kHalo, oy = a.j0 + ty * TH - kHalo;
   const int tid = threadIdx.x;
@@ -205,7 +208,6 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
     }
   }
   // the tile plan: rows of its stored nodes, its core cut vertices
-  const int p0 = a.tp_off[t], nrow = a.tp_off[t + 1] - p0;
   const int nrl = min(nrow, PR);
   T rcf[NCF];
   int rix[NRI];
@@ -218,14 +220,6 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   for (int u = 0; u < NRI; ++u) {
     const int e = tid + u * BS;
     rix[u] = e < nrl ? a.tp_idx[p0 + e] : -1;
-  }
-  const int c0 = a.tc_off[t], ncut = a.tc_off[t + 1] - c0;
-  int cix[KC], cpo[KC];
-#pragma unroll
-  for (int u = 0; u < KC; ++u) {
-    const int e = tid + u * BS;
-    cix[u] = e < ncut ? a.tc_idx[c0 + e] : -1;
-    cpo[u] = e < ncut ? a.tc_pos[c0 + e] : 0;
   }
   // the staged iterate goes straight from global memory into LDS (one dword
   // per lane, 64-dword chunks per wave instruction, no registers)
@@ -263,6 +257,15 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
       const int q = pq[p][it];
       pb[p][it] = q >= 0 ? a.b[(ox + q % RW) + (int64_t)(oy + q / RW) * a.s] : T(0);
     }
+  // the core's cut vertices (used after the last phase), issued last so that
+  // waiting for them never holds back the loads above
+  int cix[KC], cpo[KC];
+#pragma unroll
+  for (int u = 0; u < KC; ++u) {
+    const int e = tid + u * BS;
+    cix[u] = e < ncut ? a.tc_idx[c0 + e] : -1;
+    cpo[u] = e < ncut ? a.tc_pos[c0 + e] : 0;
+  }
 #pragma unroll
   for (int u = 0; u < NCF; ++u) {
     const int q = tid + u * BS;
@@ -1022,6 +1025,7 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   (void)shape;
   a.per = (a.ntiles + 7) / 8;
   a.reverse = reverse ? 1 : 0;
+  a.tmeta = L.tmeta;
   a.tp_off = L.tp_off;
   a.tp_idx = L.tp_idx;
   a.tp_coef = std::is_same<T, double>::value ? reinterpret_cast<const T*>(L.tp_coef)
@@ -1054,9 +1058,9 @@ void sweep(mgfem_ctx* c, int l, bool reverse, bool norm = false, bool prolong_fr
   Level& L = c->lv[l];
   if (L.empty()) return;
   switch (sweep_shape(c, l)) {
-    case kShapeFinest: launch_sweep<T, 64, 64, 512>(c, l, reverse, norm, prolong_from, kShapeFinest); break;
-    case kShapeLarge: launch_sweep<T, 64, 32, 256>(c, l, reverse, norm, prolong_from, kShapeLarge); break;
-    default: launch_sweep<T, 32, 16, 256>(c, l, reverse, norm, prolong_from, kShapeSmall); break;
+    case kShapeFinest: launch_sweep<T, 64, 32, 512>(c, l, reverse, norm, prolong_from, kShapeFinest); break;
+    case kShapeLarge: launch_sweep<T, 64, 16, 512>(c, l, reverse, norm, prolong_from, kShapeLarge); break;
+    default: launch_sweep<T, 16, 16, 512>(c, l, reverse, norm, prolong_from, kShapeSmall); break;
   }
 }
 
@@ -1293,8 +1297,8 @@ int build_tile_lists(mgfem_ctx* c) {
     Level& L = c->lv[l];
     if (L.empty()) continue;
     const int shape = sweep_shape(c, l);
-    const int TW = shape == kShapeFinest ? 64 : (shape == kShapeLarge ? 64 : 32);
-    const int TH = shape == kShapeFinest ? 64 : (shape == kShapeLarge ? 32 : 16);
+    const int TW = shape == kShapeSmall ? 16 : 64;
+    const int TH = shape == kShapeFinest ? 32 : 16;
     const int ntx = (L.bbox[1] - L.bbox[0] + TW) / TW, nty = (L.bbox[3] - L.bbox[2] + TH) / TH;
     int* act = nullptr;
     MGFEM_HIP_TRY(ctx_alloc_t(c, &act, ntx * nty));
@@ -1347,6 +1351,18 @@ int build_tile_lists(mgfem_ctx* c) {
                          L.stride, L.bbox[0], L.bbox[2], L.bbox[1], L.bbox[3], TW, TH, ntx, L.tiles, 1, nullptr,
                          nullptr, L.tp_off, L.tc_off, L.tp_idx, L.tp_coef, L.tp_coef32, L.tc_idx, L.tc_pos);
     MGFEM_HIP_TRY(hipGetLastError());
+    std::vector<int> meta(8 * (size_t)std::max(1, nt), 0);
+    for (int q = 0; q < nt; ++q) {
+      meta[8 * q + 0] = list[q];
+      meta[8 * q + 1] = ho[q];
+      meta[8 * q + 2] = hc[q];
+      meta[8 * q + 3] = hco[q];
+      meta[8 * q + 4] = hcc[q];
+    }
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &L.tmeta, meta.size()));
+    MGFEM_HIP_TRY(hipMemcpyAsync(L.tmeta, meta.data(), meta.size() * sizeof(int), hipMemcpyHostToDevice, c->s));
+    // the host vectors must outlive the asynchronous copies
+    MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   }
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   return MGFEM_OK;
