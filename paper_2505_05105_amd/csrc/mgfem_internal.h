@@ -114,6 +114,10 @@ struct Level {
   // per list entry: tile, first stored row, stored rows, first cut vertex, cut
   // vertices (and 3 unused): one 32-byte scalar load gives a sweep tile all of it
   int* tmeta = nullptr;
+  // residual-restriction tiles of this level (coarse tiles of the next level
+  // that hold an active coarse node)
+  int* rr_tiles = nullptr;
+  int rr_ntiles = 0;
   int* tc_idx = nullptr;
   int* tc_pos = nullptr;
   int tp_max = 0, tc_max = 0;

@@ -509,6 +509,8 @@ struct ResArgs {
   int Nc, sc;
   int I0, J0, I1, J1;  // coarse bounding box
   int ntx, nty, per;
+  const int* tiles;  // coarse tiles that hold an active coarse node
+  int ntiles;
 };
 
 template <class T, int RW>
@@ -517,18 +519,19 @@ __device__ inline T row_product(const T* __restrict__ A, int64_t n, int64_t k, b
   return T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) * T(1.0 / 3.0);
 }
 
-template <class T, int CW, int CH>
-__global__ __launch_bounds__(256) void k_resrestrict(ResArgs<T> a) {
+template <class T, int CW, int CH, int BS>
+__global__ __launch_bounds__(BS) void k_resrestrict(ResArgs<T> a) {
   constexpr int RW = 2 * CW + 1, RH = 2 * CH + 1;  // fine residual region
   constexpr int UW = RW + 2, UH = RH + 2;          // fine x region
-  constexpr int NU = (UW * UH + 255) / 256, NR = (RW * RH + 255) / 256;
+  constexpr int NU = (UW * UH + BS - 1) / BS, NR = (RW * RH + BS - 1) / BS;
   __shared__ T su[UH * UW];
   __shared__ T sr[RH * RW];
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
   const int t = xcd * a.per + loc;
-  if (t >= a.ntx * a.nty) return;
+  if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
+  const int tile = a.tiles[t];
   const int tid = threadIdx.x;
-  const int tx = t % a.ntx, ty = t / a.ntx;
+  const int tx = tile % a.ntx, ty = tile / a.ntx;
   const int cI0 = a.I0 + tx * CW, cJ0 = a.J0 + ty * CH;
   const int fx0 = 2 * cI0 - 1, fy0 = 2 * cJ0 - 1;  // residual region origin
   const int ux0 = fx0 - 1, uy0 = fy0 - 1;
@@ -538,32 +541,32 @@ __global__ __launch_bounds__(256) void k_resrestrict(ResArgs<T> a) {
     T ru[NU];
 #pragma unroll
     for (int it = 0; it < NU; ++it) {
-      const int q = tid + 256 * it;
+      const int q = tid + BS * it;
       const int gi = ux0 + q % UW, gj = uy0 + q / UW;
       ru[it] = (q < UW * UH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.x[gi + (int64_t)gj * a.s] : T(0);
     }
 #pragma unroll
     for (int it = 0; it < NR; ++it) {
-      const int q = tid + 256 * it;
+      const int q = tid + BS * it;
       const int gi = fx0 + q % RW, gj = fy0 + q / RW;
       rf[it] = (q < RW * RH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.fl[gi + (int64_t)gj * a.s] : 0;
     }
 #pragma unroll
     for (int it = 0; it < NR; ++it) {
-      const int q = tid + 256 * it;
+      const int q = tid + BS * it;
       const int gi = fx0 + q % RW, gj = fy0 + q / RW;
       rb[it] = (rf[it] & kFlagActive) ? a.b[gi + (int64_t)gj * a.s] : T(0);
     }
 #pragma unroll
     for (int it = 0; it < NU; ++it) {
-      const int q = tid + 256 * it;
+      const int q = tid + BS * it;
       if (q < UW * UH) su[q] = ru[it];
     }
   }
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < NR; ++it) {
-    const int q = tid + 256 * it;
+    const int q = tid + BS * it;
     if (q >= RW * RH) break;
     const int ri = q % RW, rj = q / RW;
     T r = T(0);
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(256) void k_resrestrict(ResArgs<T> a) {
     sr[q] = r;
   }
   __syncthreads();
-  for (int q = tid; q < CW * CH; q += 256) {
+  for (int q = tid; q < CW * CH; q += BS) {
     const int I = cI0 + q % CW, J = cJ0 + q / CW;
     if (I > a.I1 || J > a.J1) continue;
     const int64_t kc = I + (int64_t)J * a.sc;
@@ -1109,7 +1112,7 @@ void smooth(mgfem_ctx* c, int l, bool reverse) {
   }
 }
 
-template <class T, int CW, int CH>
+template <class T, int CW, int CH, int BS>
 void launch_resrestrict(mgfem_ctx* c, int l) {
   Level& L = c->lv[l];
   Level& C = c->lv[l + 1];
@@ -1135,8 +1138,11 @@ void launch_resrestrict(mgfem_ctx* c, int l) {
   a.J1 = C.bbox[3];
   a.ntx = (a.I1 - a.I0 + CW) / CW;
   a.nty = (a.J1 - a.J0 + CH) / CH;
-  a.per = (a.ntx * a.nty + 7) / 8;
-  hipLaunchKernelGGL((k_resrestrict<T, CW, CH>), dim3(8 * a.per), dim3(256), 0, c->s, a);
+  a.tiles = L.rr_tiles;
+  a.ntiles = L.rr_ntiles;
+  if (a.ntiles == 0) return;
+  a.per = (a.ntiles + 7) / 8;
+  hipLaunchKernelGGL((k_resrestrict<T, CW, CH, BS>), dim3(8 * a.per), dim3(BS), 0, c->s, a);
 }
 
 template <class T>
@@ -1197,8 +1203,8 @@ void cycle_level(mgfem_ctx* c, int l, bool reverse, bool first_sweep_done = fals
     if (s == 0 && first_sweep_done) cut_sweeps<T>(c, l, reverse);
     else smooth<T>(c, l, reverse);
   }
-  if (c->lv[l].N >= 1024) launch_resrestrict<T, 32, 16>(c, l);
-  else launch_resrestrict<T, 16, 8>(c, l);
+  if (c->lv[l].N >= 1024) launch_resrestrict<T, 32, 16, 512>(c, l);
+  else launch_resrestrict<T, 16, 8, 512>(c, l);
   // coarse-grid visits: gamma* (section 3.2); the two-grid scheme instead
   // solves the first coarse problem with coarse_cycles V-cycles from zero
   const bool two_grid = c->p.cycle == MGFEM_CYCLE_TWO_GRID && l == 0;
@@ -1363,6 +1369,28 @@ int build_tile_lists(mgfem_ctx* c) {
     MGFEM_HIP_TRY(hipMemcpyAsync(L.tmeta, meta.data(), meta.size() * sizeof(int), hipMemcpyHostToDevice, c->s));
     // the host vectors must outlive the asynchronous copies
     MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+    // residual-restriction tiles: coarse tiles (the shape launch_resrestrict
+    // uses for this level) with an active coarse node
+    Level& C = c->lv[l + 1];
+    if (!C.empty()) {
+      const int CW = L.N >= 1024 ? 32 : 16, CH = L.N >= 1024 ? 16 : 8;
+      const int cnx = (C.bbox[1] - C.bbox[0] + CW) / CW, cny = (C.bbox[3] - C.bbox[2] + CH) / CH;
+      int* cact = nullptr;
+      MGFEM_HIP_TRY(ctx_alloc_t(c, &cact, cnx * cny));
+      hipLaunchKernelGGL(k_tile_active, dim3(cnx * cny), dim3(256), 0, c->s, C.flags, C.stride, C.bbox[0], C.bbox[2],
+                         C.bbox[1], C.bbox[3], CW, CH, cnx, cny, cact);
+      std::vector<int> hca(cnx * cny);
+      MGFEM_HIP_TRY(hipMemcpyAsync(hca.data(), cact, hca.size() * sizeof(int), hipMemcpyDeviceToHost, c->s));
+      MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+      std::vector<int> rl;
+      for (int q = 0; q < cnx * cny; ++q)
+        if (hca[q]) rl.push_back(q);
+      MGFEM_HIP_TRY(ctx_alloc_t(c, &L.rr_tiles, std::max<size_t>(1, rl.size())));
+      if (!rl.empty())
+        MGFEM_HIP_TRY(hipMemcpyAsync(L.rr_tiles, rl.data(), rl.size() * sizeof(int), hipMemcpyHostToDevice, c->s));
+      MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+      L.rr_ntiles = (int)rl.size();
+    }
   }
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   return MGFEM_OK;
