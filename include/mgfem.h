@@ -161,7 +161,8 @@ int mgfem_setup(const double* psi_dev, int32_t N, const mgfem_params* p, void* s
  * the load matrix of g_N.  Coarse levels assembled on their own grids
  * (MGFEM_COARSE_REDISCRETISED) take chi at their nodes like psi.
  * Solve such a handle with mgfem_solve_mixed_bc (mgfem_solve: g_N = 0).
- * Errors: as mgfem_setup.
+ * Errors: as mgfem_setup; INVALID_ARG when no segment is a Dirichlet segment
+ * (the problem would be singular: constants solve the homogeneous one).
  */
 int mgfem_setup_mixed_bc(const double* psi_dev, const double* chi_dev, int32_t N, const mgfem_params* p,
                          void* stream, mgfem_handle* out);

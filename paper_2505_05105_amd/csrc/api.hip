@@ -322,6 +322,11 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   e0 = e1 = nullptr;
+  if (chi_dev && op_kind == kOpAssembled && st.dirichlet_cells == 0) {
+    c->last_error = "no interface segment is a Dirichlet segment: with Neumann data on the whole boundary the "
+                    "problem is singular";
+    return bail(MGFEM_ERR_INVALID_ARG);
+  }
   if (st.coarse_status != 0) {
     c->last_error = "non-positive pivot in the Cholesky factor of the coarsest operator";
     return bail(MGFEM_ERR_SINGULAR_COARSE);

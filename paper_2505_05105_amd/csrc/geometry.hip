@@ -431,12 +431,13 @@ __device__ inline void load_cell_psi(const double* psi, int stride, int ci, int 
 __global__ void k_classify(const double* __restrict__ psi, const double* __restrict__ chi, int N,
                            mgfem_params p, double h, uint8_t* __restrict__ ctype, double* __restrict__ clam,
                            uint8_t* __restrict__ cellcut, Stats* st) {
-  __shared__ unsigned int cnt[7];
+  __shared__ unsigned int cnt[7], ndir;
   __shared__ unsigned long long mint, maxl;
   if (threadIdx.x < 7) cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) {
     mint = 0x7ff0000000000000ull;
     maxl = 0;
+    ndir = 0;
   }
   __syncthreads();
   int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -463,6 +464,7 @@ __global__ void k_classify(const double* __restrict__ psi, const double* __restr
       }
       double lh = lambda_h_rule(ps, cc.theta, t, p.stab_rule, p.gamma, p.lambda_fixed, h, chat_eig);
       lam = all_neumann(cc) ? 0.0 : lh / h;
+      if (!all_neumann(cc)) atomicAdd(&ndir, 1u);
       double tmin = 2.0;
       for (int e = 0; e < 4; ++e)
         if (cc.theta[e] >= 0.0) tmin = fmin(tmin, cc.theta[e]);
@@ -477,6 +479,7 @@ __global__ void k_classify(const double* __restrict__ psi, const double* __restr
   __syncthreads();
   if (threadIdx.x < 7 && cnt[threadIdx.x])
     atomicAdd(&st->counts[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+  if (threadIdx.x == 0 && ndir) atomicAdd(&st->dirichlet_cells, (unsigned long long)ndir);
   if (threadIdx.x == 0) {
     if (mint != 0x7ff0000000000000ull) atomicMin(&st->min_theta_bits, mint);
     if (maxl) atomicMax(&st->max_lambda_bits, maxl);

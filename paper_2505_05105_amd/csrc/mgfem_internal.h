@@ -189,6 +189,7 @@ struct Stats {
   unsigned long long max_lambda_bits;  // float64 bits of the maximum lambda
   int coarse_status;                   // 0 ok, 1 singular
   int coarse_n;
+  unsigned long long dirichlet_cells;  // cut cells with a Dirichlet segment
 };
 
 struct BatchDevice {

@@ -184,3 +184,14 @@ def test_handles_without_indicator_ignore_neumann_data():
     sd = mg.Solver(p.psi, N, chi=-np.ones(s.n))
     u3, h3 = sd.solve(p.f, p.g, gN=p.gN, tol=1e-10)
     assert torch.equal(u1, u3) and np.array_equal(h1, h3)
+
+
+def test_all_neumann_boundary_is_rejected():
+    """With Neumann data on the whole boundary constants solve the homogeneous
+    problem; the setup refuses it instead of factorising a singular matrix."""
+    mg = _gpu()
+    N = 64
+    psi = W.circle(N, radius=0.55)
+    with pytest.raises(mg.MgfemError) as e:
+        mg.Solver(psi, N, chi=np.ones((N + 1) ** 2))
+    assert e.value.code == mg._lib.ERR_INVALID_ARG
