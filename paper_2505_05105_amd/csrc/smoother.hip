@@ -117,12 +117,11 @@ __device__ inline T gs_value(const T* __restrict__ A, int64_t n, int64_t k, bool
   return (T(3) * bv + q1_neighbours<T, RW>(su, q)) * T(0.125);
 }
 
-// One full four-colour sweep of a TW x TH tile.  Only the iterate is staged in
-// LDS (tile plus a halo of 4); each thread prefetches the flags and
-// right-hand sides of the nodes it updates in the four phases into
-// registers, so a block needs about 8 bytes of LDS per staged node and six
-// blocks fit on a CU.  A node's value is final after the phase of its colour,
-// so core nodes are written out right there.
+// One full four-colour sweep of a TW x TH tile.  The iterate is staged in
+// LDS (tile plus a halo of 4) together with the tile plan's stored rows; each
+// thread prefetches the flags and right-hand sides of the nodes it updates in
+// the four phases into registers.  A node's value is final after the phase of
+// its colour, so core nodes are written out right there.
 //  prolong: the staged iterate is x + P x_c (the coarse-grid correction is
 //           applied on the fly, so the first post-smoothing sweep needs no
 //           separate prolongation pass).
