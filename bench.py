@@ -30,12 +30,17 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic.json")
 
 
 def source_hash():
-    """Hash of the sources of the profiled kernel (counters go stale when they change)."""
+    """Hash of the code of the profiled kernel's sources, comments and blank
+    space left out (counters go stale when the code changes)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in ("smoother.hip", "mgfem_internal.h"):
-        with open(os.path.join(ROOT, "paper_2505_05105_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2505_05105_amd", "csrc", name)) as fh:
+            text = fh.read()
+        text = re.sub(r"//[^\n]*", "", text)
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
