@@ -145,3 +145,26 @@ def test_rediscretised_cycles_match_oracle():
     assert len(hist) == len(ref.hist)
     assert rel_max(u.cpu().numpy(), ref.u) < 1e-10
     assert np.abs(hist[1:] / hist[:-1] - ref.rho).max() < 0.02
+
+
+def test_rediscretised_adjoint_and_mixed_precision():
+    """The transposed cycle with re-discretised coarse operators (symmetric,
+    R = P^T) against the oracle's, and the mixed-precision solve with them
+    reaching the float64 tolerance."""
+    mg = _gpu()
+    from oracle import adjoint as oadj
+    N = 128
+    p = W.flower_mms(N)
+    d = oasm.assemble(p.psi, N)
+    H = omg.build_hierarchy(d, rediscretise=(p.psi, {}))
+    s = mg.Solver(p.psi, N, coarse_op=mg.COARSE_REDISCRETISED)
+    r = np.random.default_rng(11).standard_normal(d.n) * d.active
+    _, _, lam, _ = s.adjoint(r, tol=-1.0, max_cycles=3)
+    ref = oadj.adjoint_solve(H, r, tol=-1.0, max_cycles=3)
+    assert rel_max(lam.cpu().numpy(), ref.u) < 1e-10
+    F = d.rhs(p.f, p.g)
+    sm = mg.Solver(p.psi, N, coarse_op=mg.COARSE_REDISCRETISED, precision=mg.PREC_MIXED)
+    u, hist = sm.solve(p.f, p.g, tol=1e-10, max_cycles=60)
+    assert sm.last_status == 0 and hist[-1] <= 1e-10 * np.abs(F).max()
+    direct = omg.solve(H, F, tol=1e-14, max_cycles=100).u
+    assert rel_max(u.cpu().numpy(), direct) < 1e-8

@@ -195,3 +195,17 @@ def test_all_neumann_boundary_is_rejected():
     with pytest.raises(mg.MgfemError) as e:
         mg.Solver(psi, N, chi=np.ones((N + 1) ** 2))
     assert e.value.code == mg._lib.ERR_INVALID_ARG
+
+
+def test_w_cycle_with_neumann_segments():
+    mg = _gpu()
+    N = 128
+    p = W.leaf_mms(N)
+    d = oasm.assemble(p.psi, N, chi=p.chi)
+    H = omg.build_hierarchy(d)
+    F = d.rhs(p.f, p.g, p.gN)
+    s = mg.Solver(p.psi, N, chi=p.chi, cycle=mg.CYCLE_W)
+    u, hist = s.solve(p.f, p.g, gN=p.gN, tol=-1.0, max_cycles=3)
+    ref = omg.solve(H, F, tol=-1.0, max_cycles=3, gamma_star=2)
+    assert rel_max(u.cpu().numpy(), ref.u) < 1e-11
+    np.testing.assert_allclose(hist, ref.hist, rtol=1e-8, atol=50 * 2.2e-16 * hist[0])
