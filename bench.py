@@ -210,8 +210,8 @@ def _cpu_name():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU runs are not "
-                                   "part of this build (--gpus 1)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); the solver has no "
+                                   "multi-GPU path"}))
         sys.exit(2)
     import numpy as np
     import torch

@@ -4,15 +4,17 @@
  * given by a level set (Dilip & Coco, "Multigrid methods for the ghost finite
  * element approximation of elliptic problems", arXiv 2505.05105).
  *
- * Problem (section 2): -lap u = f in Omega = {psi < 0}, u = g on its boundary,
- * discretised with Q1 elements on the active cells of a uniform N x N grid
- * over a box, Dirichlet data imposed weakly by Nitsche's method (eqs.
- * disc_bil_form, disc_rhs) with the cell-wise stabilisation
- * lambda_K = gamma C(K) (section 5.2), after snapping back to grid (section 2).
+ * Problem (section 2): -lap u = f in Omega = {psi < 0}, u = g on its boundary
+ * (or u = g_D on a Dirichlet part and n . grad u = g_N on a Neumann part,
+ * mgfem_setup_mixed_bc), discretised with Q1 elements on the active cells of
+ * a uniform N x N grid over a box, Dirichlet data imposed weakly by Nitsche's
+ * method (eqs. disc_bil_form, disc_rhs) with the cell-wise stabilisation
+ * lambda_K = gamma C(K) or one global lambda (section 5.2), after snapping
+ * back to grid (section 2).
  * Solver (sections 3 and 5): Gauss-Seidel smoothing in four colours plus eta
  * extra sweeps on the vertices of cut cells, restriction by the transposed
- * bilinear prolongation, Galerkin coarse operators R A P, exact solve on the
- * coarsest grid, V- or W-cycles.
+ * bilinear prolongation, Galerkin (or re-discretised) coarse operators, exact
+ * solve on the coarsest grid, V- or W-cycles or the two-grid scheme.
  *
  * Conventions shared by every call:
  *  - Grid arrays are float64 arrays in device memory of length (N+1)^2; node
@@ -52,7 +54,7 @@ enum mgfem_status {
   MGFEM_ERR_DIVERGED = 5,        /* non-finite residual, or growth over 3 cycles */
   MGFEM_ERR_SINGULAR_COARSE = 6, /* non-positive pivot in the coarsest Cholesky */
   MGFEM_ERR_EMPTY_DOMAIN = 7,    /* no node with psi < 0 after snapping */
-  MGFEM_ERR_UNSUPPORTED = 8      /* option not available in this build */
+  MGFEM_ERR_UNSUPPORTED = 8      /* option not supported by the library */
 };
 
 /* Stabilisation rule for lambda_K = gamma C(K) (section 5.2). */
