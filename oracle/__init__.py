@@ -13,15 +13,16 @@ Layout (all numpy / scipy, float64):
                  parameters", eqs. c_triangle / c_pentagon and the
                  quadrilateral formula)
 * ``quadrature`` exact integration of Q1 basis products on polygons/segments
-* ``assembly``   element matrices and global sparse A, M, G
-                 (eqs. disc_bil_form / disc_rhs)
+* ``assembly``   element matrices and global sparse A, M, G, the Neumann
+                 load GN of mixed boundaries (eqs. disc_bil_form / disc_rhs),
+                 the global generalised eigenproblem of section 5.2
 * ``multigrid``  bilinear prolongation, Galerkin hierarchy (eq. galerkin),
                  four-colour and lexicographic Gauss-Seidel, extra smoothing on
                  cut cells, two-grid scheme (Algorithm 1), V- and W-cycles,
                  convergence factors (section 3)
-* ``adjoint``    misfit, transposed V-cycle, gradients w.r.t. f and g
+* ``adjoint``    misfit, transposed V-cycle, gradients w.r.t. f, g and g_N
 
-Readings where the paper is silent are listed in the design doc and repeated at the
-function that implements each of them.
+Readings where the paper is silent are stated at the function that implements
+each of them.
 """
 from . import geometry, quadrature, assembly, multigrid, adjoint  # noqa: F401
