@@ -168,3 +168,21 @@ def test_rediscretised_adjoint_and_mixed_precision():
     assert sm.last_status == 0 and hist[-1] <= 1e-10 * np.abs(F).max()
     direct = omg.solve(H, F, tol=1e-14, max_cycles=100).u
     assert rel_max(u.cpu().numpy(), direct) < 1e-8
+
+
+@pytest.mark.parametrize("name", ["paper_flower", "hourglass"])
+def test_paper_convergence_other_geometries_on_gpu(name):
+    """The flower and the hourglass of section 5.3 on [-1, 1]^2, h = 2^-5,
+    gamma = 2: the two-grid factor with eta = 4 is at most about 0.1 and
+    several times smaller than without extra sweeps; both are the oracle's
+    within 0.02."""
+    mg = _gpu()
+    N = 64
+    psi = W.paper_flower(N) if name == "paper_flower" else W.hourglass(N)
+    d = oasm.assemble(psi, N)
+    H2 = omg.two_grid(d)
+    rho4 = _gpu_rho(mg, psi, N, W.BOX, cycle=mg.CYCLE_TWO_GRID, eta=4)
+    rho0 = _gpu_rho(mg, psi, N, W.BOX, cycle=mg.CYCLE_TWO_GRID, eta=0)
+    assert rho4 < 0.12 and rho0 > 3 * rho4
+    assert abs(rho4 - omg.rho_protocol(H2, eta=4)) < 0.02
+    assert abs(rho0 - omg.rho_protocol(H2, eta=0)) < 0.02
