@@ -22,7 +22,7 @@ from ._lib import (COARSE_GALERKIN, COARSE_REDISCRETISED, CYCLE_TWO_GRID, CYCLE_
                    PREC_FP64, PREC_MIXED, STAB_FIXED, STAB_GLOBAL, STAB_LOCAL_EIG, STAB_PAPER, MgfemError,
                    default_params)
 
-__all__ = ["Solver", "BatchedSolver", "GhostFEMSolve", "MgfemError", "default_params"]
+__all__ = ["Solver", "BatchedSolver", "GhostFEMSolve", "GhostFEMSolveMixed", "MgfemError", "default_params"]
 
 CELL_TYPES = ("external", "triangle", "quadrilateral", "pentagon", "internal",
               "saddle_split", "saddle_hexagon")
@@ -203,6 +203,24 @@ class GhostFEMSolve(torch.autograd.Function):
     def backward(ctx, grad_u):
         df, dg, _, _ = ctx.solver.adjoint(grad_u.contiguous(), tol=-1.0, max_cycles=ctx.cycles)
         return df, dg, None, None, None
+
+
+class GhostFEMSolveMixed(torch.autograd.Function):
+    """Mixed boundaries: u = B_k (M f + G g_D + GN g_N) with k cycles on a
+    solver set up with an indicator; backward gives dL/df = M lam,
+    dL/dg_D = G^T lam and dL/dg_N = GN^T lam (mgfem_adjoint_neumann)."""
+
+    @staticmethod
+    def forward(ctx, f, gD, gN, solver, tol=1e-10, max_cycles=50):
+        u, hist = solver.solve(f.detach(), gD.detach(), tol=tol, max_cycles=max_cycles, gN=gN.detach())
+        ctx.solver = solver
+        ctx.cycles = len(hist) - 1
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        df, dg, lam, _ = ctx.solver.adjoint(grad_u.contiguous(), tol=-1.0, max_cycles=ctx.cycles)
+        return df, dg, ctx.solver.neumann_gradient(lam), None, None, None
 
 
 class BatchedSolver:

@@ -209,3 +209,35 @@ def test_w_cycle_with_neumann_segments():
     ref = omg.solve(H, F, tol=-1.0, max_cycles=3, gamma_star=2)
     assert rel_max(u.cpu().numpy(), ref.u) < 1e-11
     np.testing.assert_allclose(hist, ref.hist, rtol=1e-8, atol=50 * 2.2e-16 * hist[0])
+
+
+def test_autograd_with_neumann_data():
+    """GhostFEMSolveMixed: gradients with respect to f, g_D and g_N against
+    central differences of the misfit (J is quadratic in the data for a fixed
+    cycle count, so only rounding remains)."""
+    mg = _gpu()
+    N = 64
+    k = 6
+    p = W.annulus_mms(N)
+    s = mg.Solver(p.psi, N, chi=p.chi)
+    ut = torch.tensor(W.adjoint_target(N), device="cuda:0")
+    data = [torch.tensor(v, device="cuda:0", requires_grad=True) for v in (p.f, p.g, p.gN)]
+    u = mg.GhostFEMSolveMixed.apply(*data, s, -1.0, k)
+    _, dJdu = s.misfit(u.detach(), ut)
+    (u * dJdu).sum().backward()
+
+    def J_at(vals):
+        uu = mg.GhostFEMSolveMixed.apply(*vals, s, -1.0, k)
+        return s.misfit(uu.detach(), ut)[0]
+
+    base = [t.detach() for t in data]
+    J0 = J_at(base)
+    eps = 1e-6
+    for q, dv in enumerate(W.random_directions((N + 1) ** 2, 3, seed=4)):
+        dvt = torch.tensor(dv, device="cuda:0")
+        for which in range(3):
+            plus = [b + eps * dvt if w == which else b for w, b in enumerate(base)]
+            minus = [b - eps * dvt if w == which else b for w, b in enumerate(base)]
+            fd = (J_at(plus) - J_at(minus)) / (2 * eps)
+            an = float(data[which].grad @ dvt)
+            assert an == pytest.approx(fd, rel=1e-6, abs=50 * 2.2e-16 * abs(J0) / eps), (q, which)
