@@ -159,6 +159,12 @@ __global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* 
   }
 }
 
+// 16 bytes per lane from global memory straight into LDS at dst + 16 * lane
+// (a device function: the builtin's 16-byte form exists only for gfx950)
+__device__ inline void lds_load16(const void* src, void* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
 template <class T, int TW, int TH, int BS>
 __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   constexpr int RW = TW + 2 * kHalo, RH = TH + 2 * kHalo;
@@ -168,13 +174,15 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   constexpr int PR = 255;  // stored rows of a tile kept in LDS (slot 255: read A)
   constexpr int NCF = (9 * PR + BS - 1) / BS, NRI = (PR + BS - 1) / BS;
   constexpr int KC = 2;                             // core cut vertices prefetched per thread
-  constexpr int ES = (int)sizeof(T) / 4;            // dwords per value
-  constexpr int NDW = RW * RH * ES, NCH = (NDW + 63) / 64;
-  __shared__ __align__(16) T su[NCH * 64 / ES];  // the region, rounded up to whole 64-dword chunks
-  // coarse tile under the region (fused prolongation): parents of the region's nodes
-  constexpr int CW = RW / 2 + 2, CH = RH / 2 + 2;
-  constexpr int NCDW = CW * CH * ES, NCCH = (NCDW + 63) / 64;
-  __shared__ __align__(16) T sxc[NCCH * 64 / ES];
+  constexpr int G = 16 / (int)sizeof(T);  // values per 16-byte lane load: G consecutive nodes of a row
+  static_assert(RW % G == 0, "region rows hold whole 16-byte groups");
+  constexpr int NQ = RW * RH / G, NCH = (NQ + 63) / 64;
+  __shared__ __align__(16) T su[NCH * 64 * G];  // the region, rounded up to whole 64-group chunks
+  // coarse tile under the region (fused prolongation): parents of the region's
+  // nodes, rows padded to whole groups
+  constexpr int CW = (RW / 2 + 2 + G - 1) / G * G, CH = RH / 2 + 2;
+  constexpr int NCQ = CW * CH / G, NCCH = (NCQ + 63) / 64;
+  __shared__ __align__(16) T sxc[NCCH * 64 * G];
   __shared__ T scf[9 * PR];
   __shared__ uint8_t sslot[RH * RW];  // stored node: its row in scf (255: read A); others unused
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
@@ -220,33 +228,26 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
     const int e = tid + u * BS;
     rix[u] = e < nrl ? a.tp_idx[p0 + e] : -1;
   }
-  // the staged iterate goes straight from global memory into LDS (one dword
-  // per lane, 64-dword chunks per wave instruction, no registers)
-  {
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int ch = wave; ch < NCH; ch += BS / 64) {
-      const int dw = ch * 64 + lane;
-      const int e = dw / ES;
-      const int gi = ox + e % RW, gj = oy + e / RW;
-      const bool in = dw < NDW && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N;
-      const char* src = reinterpret_cast<const char*>(in ? a.xin + gi + (int64_t)gj * a.s : a.zero) + 4 * (dw % ES);
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(su) + ch * 256),
-                                       4, 0, 0);
-    }
+  // the staged iterate goes straight from global memory into LDS: 16 bytes
+  // (one group) per lane, 64 groups per wave instruction, no registers. A
+  // group that lies only partly on the grid loads zeros here; its on-grid
+  // nodes are filled in after the loads have landed.
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int ch = wave; ch < NCH; ch += BS / 64) {
+    const int e = (ch * 64 + lane) * G;
+    const int gi = ox + e % RW, gj = oy + e / RW;
+    const bool in = e < RW * RH && gi >= 0 && gj >= 0 && gi + G - 1 <= a.N && gj <= a.N;
+    lds_load16(in ? a.xin + gi + (int64_t)gj * a.s : a.zero, su + ch * 64 * G);
   }
   // the coarse iterate under the region, the same way (fused prolongation)
   const int cox = ox >> 1, coy = oy >> 1;  // floor: the parents of the region's first node
+  const int Nc = a.N >> 1;
   if (a.xc) {
-    const int lane = tid & 63, wave = tid >> 6;
-    const int Nc = a.N >> 1;
     for (int ch = wave; ch < NCCH; ch += BS / 64) {
-      const int dw = ch * 64 + lane;
-      const int e = dw / ES;
+      const int e = (ch * 64 + lane) * G;
       const int I = cox + e % CW, J = coy + e / CW;
-      const bool in = dw < NCDW && I >= 0 && J >= 0 && I <= Nc && J <= Nc;
-      const char* src = reinterpret_cast<const char*>(in ? a.xc + I + (int64_t)J * a.sc : a.zero) + 4 * (dw % ES);
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(sxc) + ch * 256),
-                                       4, 0, 0);
+      const bool in = e < CW * CH && I >= 0 && J >= 0 && I + G - 1 <= Nc && J <= Nc;
+      lds_load16(in ? a.xc + I + (int64_t)J * a.sc : a.zero, sxc + ch * 64 * G);
     }
   }
 #pragma unroll
@@ -276,6 +277,25 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   for (int e = PR + tid; e < nrow; e += BS) sslot[a.tp_idx[p0 + e]] = (uint8_t)PR;  // beyond the LDS rows
   __builtin_amdgcn_s_waitcnt(0);  // the global->LDS loads of this thread have landed
   __syncthreads();
+  if (ox < 0 || ox + RW > a.N + 1 || (a.xc && (cox < 0 || cox + CW > Nc + 1))) {
+    // the tile meets a side of the grid: on-grid nodes of straddling groups
+    for (int ch = wave; ch < NCH; ch += BS / 64) {
+      const int e = (ch * 64 + lane) * G;
+      const int gi = ox + e % RW, gj = oy + e / RW;
+      if (e < RW * RH && gj >= 0 && gj <= a.N && (gi < 0 || gi + G - 1 > a.N))
+        for (int v = 0; v < G; ++v)
+          if (gi + v >= 0 && gi + v <= a.N) su[e + v] = a.xin[gi + v + (int64_t)gj * a.s];
+    }
+    if (a.xc)
+      for (int ch = wave; ch < NCCH; ch += BS / 64) {
+        const int e = (ch * 64 + lane) * G;
+        const int I = cox + e % CW, J = coy + e / CW;
+        if (e < CW * CH && J >= 0 && J <= Nc && (I < 0 || I + G - 1 > Nc))
+          for (int v = 0; v < G; ++v)
+            if (I + v >= 0 && I + v <= Nc) sxc[e + v] = a.xc[I + v + (int64_t)J * a.sc];
+      }
+    __syncthreads();
+  }
   if (a.xc) {
     // + P x_c: bilinear interpolation from the (up to) four coarse parents,
     // written without branches (for an even index both parents coincide)
