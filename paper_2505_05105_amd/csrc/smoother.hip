@@ -763,15 +763,16 @@ __device__ inline T lds_gs_reg(const WgLev<T>& L, int q, int16_t sl, T bv) {
   return (T(3) * bv + nb) * T(0.125);
 }
 
-// One smoothing step of a level held in LDS.  Each thread first loads, for
-// every colour of the full and the cut list, the index, row slot and
-// right-hand side of its first kWgCache nodes into registers; a colour phase
-// then only reads x and the stored coefficients (independent LDS reads) before
-// its barrier.  Nodes beyond the cached ones take the plain path.
+// nsteps smoothing steps of a level held in LDS.  Each thread first loads,
+// for every colour of the full and the cut list, the index, row slot and
+// right-hand side of its first kWgCache nodes into registers (once for all
+// steps: they share the right-hand side); a colour phase then only reads x and
+// the stored coefficients (independent LDS reads) before its barrier.  Nodes
+// beyond the cached ones take the plain path.
 constexpr int kWgCache = 2;
 
 template <class T>
-__device__ void wg_smooth(const WgLev<T>& L, int eta, bool reverse) {
+__device__ void wg_smooth(const WgLev<T>& L, int eta, bool reverse, int nsteps) {
   int qf[4][kWgCache], qc[4][kWgCache];
   int16_t sf[4][kWgCache], sc[4][kWgCache];
   T bf[4][kWgCache], bc[4][kWgCache];
@@ -811,18 +812,20 @@ __device__ void wg_smooth(const WgLev<T>& L, int eta, bool reverse) {
     }
     __syncthreads();
   };
-  if (!reverse) {
+  for (int st = 0; st < nsteps; ++st) {
+    if (!reverse) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) full(c);
-    for (int e = 0; e < eta; ++e)
+      for (int c = 0; c < 4; ++c) full(c);
+      for (int e = 0; e < eta; ++e)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) cut(c);
-  } else {
-    for (int e = 0; e < eta; ++e)
+        for (int c = 0; c < 4; ++c) cut(c);
+    } else {
+      for (int e = 0; e < eta; ++e)
 #pragma unroll
-      for (int c = 3; c >= 0; --c) cut(c);
+        for (int c = 3; c >= 0; --c) cut(c);
 #pragma unroll
-    for (int c = 3; c >= 0; --c) full(c);
+      for (int c = 3; c >= 0; --c) full(c);
+    }
   }
 }
 
@@ -904,7 +907,7 @@ __device__ void wg_cycle(const CoarseArgs<T>& a, const int* sdesc, unsigned char
         continue;
       }
       const WgLev<T> C = wg_level<T>(sdesc + kDesc * (l + 1), base);
-      for (int s = 0; s < pre; ++s) wg_smooth<T>(L, a.eta, a.reverse);
+      wg_smooth<T>(L, a.eta, a.reverse, pre);
       wg_restrict<T>(L, C);
       visits &= ~(0xfull << (4 * l));
       ++l;
@@ -920,7 +923,7 @@ __device__ void wg_cycle(const CoarseArgs<T>& a, const int* sdesc, unsigned char
     const WgLev<T> L = wg_level<T>(sdesc + kDesc * l, base);
     const WgLev<T> C = wg_level<T>(sdesc + kDesc * (l + 1), base);
     wg_prolong<T>(L, C);
-    for (int s = 0; s < post; ++s) wg_smooth<T>(L, a.eta, a.reverse);
+    wg_smooth<T>(L, a.eta, a.reverse, post);
     --l;
   }
 }
