@@ -419,7 +419,7 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
   T* scoef = reinterpret_cast<T*>(smem + lay.coef);
   Refs8* srefs = reinterpret_cast<Refs8*>(smem + lay.refs);
   const Refs8* grefs = reinterpret_cast<const Refs8*>(a.cl_nbr) + cl_off;
-  for (int t = threadIdx.x; t < cl_cnt; t += blockDim.x) {
+  auto stage = [&](int t) {
     const int64_t k = a.cl_node[cl_off + t];
     const T v = a.snap[a.cl_q[cl_off + t]];
     const T bv = a.b[k];
@@ -434,7 +434,24 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) scoef[8 * t + e] = cf[e];
     srefs[t] = rr;
+    return k;
+  };
+  // the first KW closure nodes of this thread keep their grid index and
+  // ownership in registers for the write-back at the end
+  constexpr int KW = 2;
+  int64_t wk[KW];
+  uint8_t wo[KW];
+#pragma unroll
+  for (int u = 0; u < KW; ++u) {
+    const int t = threadIdx.x + u * blockDim.x;
+    wo[u] = 0;
+    wk[u] = 0;
+    if (t < cl_cnt) {
+      wo[u] = a.cl_own[cl_off + t];
+      wk[u] = stage(t);
+    }
   }
+  for (int t = threadIdx.x + KW * blockDim.x; t < cl_cnt; t += blockDim.x) stage(t);
   for (int t = threadIdx.x; t <= ext_cnt; t += blockDim.x) {
     T v = T(0);
     if (t < ext_cnt) {
@@ -487,7 +504,10 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
       __syncthreads();
     }
   }
-  for (int t = threadIdx.x; t < cl_cnt; t += blockDim.x)
+#pragma unroll
+  for (int u = 0; u < KW; ++u)
+    if (wo[u]) a.x[wk[u]] = vals[threadIdx.x + u * blockDim.x];
+  for (int t = threadIdx.x + KW * blockDim.x; t < cl_cnt; t += blockDim.x)
     if (a.cl_own[cl_off + t]) a.x[a.cl_node[cl_off + t]] = vals[t];
 }
 
