@@ -303,8 +303,8 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
     const int64_t tiles = (int64_t)(N / 16 + 2) * (N / 16 + 2);
     SETUP_TRY(ctx_alloc_t(c, &c->sweep_part, 2 * tiles));
   }
-  SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 4 * sizeof(double)));
-  c->red_host[2] = 0.0;
+  SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 4 * kRedSlots * sizeof(double)));
+  for (int q = 0; q < 4 * kRedSlots; ++q) c->red_host[q] = 0.0;
   {
     const char* env = std::getenv("MGFEM_NO_GRAPHS");
     c->use_graphs = !(env && env[0] && env[0] != '0');
@@ -398,13 +398,15 @@ int mgfem_destroy(mgfem_handle h) {
 
 namespace {
 
-// read c->red_out (max, sum of squares) to the host
-int read_norm(mgfem_ctx* c, double& mx, double& l2, double* raw_sum = nullptr) {
+// read the (max, sum of squares) of reduction number `want` (default: the
+// last one launched) to the host
+int read_norm(mgfem_ctx* c, double& mx, double& l2, double* raw_sum = nullptr, double want = -1.0) {
   // the reduction kernel writes (max, sum of squares, sequence number) into
-  // pinned host memory; wait for this reduction's number, then fall back to a
-  // stream synchronisation if it does not arrive (a failed launch)
-  volatile double* h = c->red_host;
-  const double want = c->red_seq;
+  // its record of pinned host memory; wait for this reduction's number, then
+  // fall back to a stream synchronisation if it does not arrive (a failed
+  // launch)
+  if (want < 0.0) want = c->red_seq;
+  volatile double* h = c->red_host + 4 * (int)((long long)want % kRedSlots);
   const auto t0 = std::chrono::steady_clock::now();
   while (h[2] != want) {
     if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(200)) {
@@ -599,18 +601,61 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   if (!std::isfinite(r0)) status = MGFEM_ERR_DIVERGED;
   const bool fused = !mixed && !reverse;  // norm of u_m from the first sweep of cycle m + 1
   bool first_done = false;
-  while (status == MGFEM_OK && !conv && m < max_cycles) {
+  // The mixed loop queues its next iteration before reading the norm it
+  // waits for (when that iteration will most likely be needed): the outer
+  // update writes the other float64 buffer, so the iterate whose norm is
+  // pending survives it and the queued iteration can be discarded.  The
+  // float64 forward cycle writes both level-0 buffers (a third buffer, which
+  // would make it safe, pushed the level-0 vectors out of the last-level
+  // cache and cost more than the launch gaps it saved) and the transposed
+  // cycle smooths its incoming iterate in place, so they wait for every norm;
+  // so do profiled solves, whose events are read per iteration.
+  const bool ahead = mixed && !c->prof.on;
+  struct Pending {
+    double seq;          // the iteration's last reduction: the norm of `result`
+    double* result;      // the iterate that norm belongs to
+    const GraphEntry* g;
+  };
+  Pending pend[2];
+  int queued = 0;
+  double* result = c->x0;  // the iterate returned when the loop stops
+  auto launch = [&](Pending& out) -> int {
     const GraphEntry* g = nullptr;
-    rc = run_iteration(c, IterKind{mixed, reverse, first_done}, &g);
-    if (rc) return rc;
+    const int e = run_iteration(c, IterKind{mixed, reverse, first_done}, &g);
+    if (e) return e;
     first_done = fused;
-    double rm;
-    rc = read_norm(c, rm, l2);
+    out.seq = c->red_seq;
+    out.g = g;
+    // fused: the closing sweep read the next iterate and wrote the other buffer
+    out.result = mixed ? L0.X[c->u_cur] : fused ? L0.X[1 - L0.cur] : L0.X[L0.cur];
+    return MGFEM_OK;
+  };
+  if (status == MGFEM_OK && !conv && m < max_cycles) {
+    rc = launch(pend[0]);
     if (rc) return rc;
-    if (g && c->prof.on) {
-      rc = prof_collect_graph(c, *g);
+    queued = 1;
+  }
+  while (queued > 0) {
+    // queue the next iteration now when it will most likely be needed: the
+    // last factor applied once more leaves the residual 4x above the target
+    if (ahead && queued == 1 && m + 1 < max_cycles) {
+      const double rho = (m > 0 && hist) ? hist[m] / std::max(hist[m - 1], 1e-300) : 1.0;
+      if (rel_tol <= 0.0 || prev * rho > 4.0 * rel_tol * bnorm) {
+        rc = launch(pend[1]);
+        if (rc) return rc;
+        queued = 2;
+      }
+    }
+    double rm;
+    rc = read_norm(c, rm, l2, nullptr, pend[0].seq);
+    if (rc) return rc;
+    if (pend[0].g && c->prof.on) {
+      rc = prof_collect_graph(c, *pend[0].g);
       if (rc) return rc;
     }
+    result = pend[0].result;
+    pend[0] = pend[1];
+    --queued;
     ++m;
     if (hist) hist[m] = rm;
     if (!std::isfinite(rm)) {
@@ -624,11 +669,16 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     }
     prev = rm;
     conv = rm <= rel_tol * bnorm;
+    if (conv) break;
+    if (queued == 0 && m < max_cycles) {
+      rc = launch(pend[0]);
+      if (rc) return rc;
+      queued = 1;
+    }
   }
-  // a speculative first sweep that is not followed by its cycle is discarded:
-  // the iterate is still in the buffer it read from
-  if (first_done) L0.cur = 1 - L0.cur;
-  launch_export(c, x, mixed ? L0.X[c->u_cur] : L0.X[L0.cur]);
+  // an iteration still queued is discarded: it never writes `result` (the
+  // export below is ordered after it on the stream)
+  launch_export(c, x, result);
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   prof_collect(c);

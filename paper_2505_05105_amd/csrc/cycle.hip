@@ -192,10 +192,11 @@ __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict_
     // device, so a replayed graph still numbers its reductions) goes last
     const double q = seq[0] + 1.0;
     seq[0] = q;
-    host_out[0] = mx;
-    host_out[1] = sm;
+    double* rec = host_out + 4 * (int)((long long)q % kRedSlots);
+    rec[0] = mx;
+    rec[1] = sm;
     __threadfence_system();
-    host_out[2] = q;
+    rec[2] = q;
     __threadfence_system();
   }
 }

@@ -161,6 +161,11 @@ struct GraphEntry {
   hipError_t err = hipSuccess; // first capture error
 };
 
+// Residual norms reach pinned host memory through a ring of records, one per
+// reduction (slot = sequence number mod kRedSlots), so that a norm the host
+// has not read yet survives the reductions of iterations queued after it.
+constexpr int kRedSlots = 8;
+
 // The coarsest levels run inside one workgroup, every array in LDS.
 constexpr int kDesc = 32;  // ints per coarse-level descriptor
 struct CoarsePlan {
@@ -241,7 +246,7 @@ struct mgfem_ctx {
   // reductions
   double* red_partial = nullptr;  // one (max, sum) pair per block of the level-0 box kernels
   double* red_out = nullptr;      // 2 doubles on device
-  double* red_host = nullptr;     // pinned: max, sum of squares, sequence number
+  double* red_host = nullptr;     // pinned: kRedSlots records (max, sum of squares, sequence number, unused)
   double red_seq = 0.0;           // sequence number of the last reduction launched
   double* red_seq_dev = nullptr;  // the same count kept on the device (bumped by each reduction kernel)
   double* sweep_part = nullptr;   // per-tile partials of the fused residual norm

@@ -69,7 +69,7 @@ struct SweepArgs {
   const int* tc_off;
   const int* tc_idx;
   const int* tc_pos;
-  const T* zero;  // at least 8 zero bytes: the source of staged nodes off the grid
+  const T* zero;  // at least 16 zero bytes: the source of staged groups off the grid
 };
 
 __device__ inline double nanmax2(double a, double b) { return (b > a || b != b) ? b : a; }
@@ -151,10 +151,11 @@ __global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* 
     out[1] = ssm[0];
     const double q = seq[0] + 1.0;  // counted on the device (graph replays)
     seq[0] = q;
-    host_out[0] = smx[0];  // straight to pinned host memory; the sequence number goes last
-    host_out[1] = ssm[0];
+    double* rec = host_out + 4 * (int)((long long)q % kRedSlots);
+    rec[0] = smx[0];  // straight to pinned host memory; the sequence number goes last
+    rec[1] = ssm[0];
     __threadfence_system();
-    host_out[2] = q;
+    rec[2] = q;
     __threadfence_system();
   }
 }

@@ -93,3 +93,33 @@ def test_profiled_replay_times_the_sweep():
     # three finest sweeps per cycle plus the speculative one of the last iteration
     assert prof["launches"] == 3 * cycles + 1
     assert prof["total_ms"] > 0 and prof["alg_bytes"] > 0
+
+
+def test_mixed_loop_queued_iteration_is_discarded():
+    """The mixed loop queues its next iteration before reading the norm it
+    waits for; when that norm meets the tolerance the queued iteration is
+    dropped.  Loose tolerances (the first cycles' factors improve on the
+    factor the queueing predicts with) must return exactly the iterate and
+    history of a run with the same number of cycles and no tolerance, the
+    profiled loop (which never queues ahead) must agree bit for bit, and the
+    solver must be unchanged for the next solve."""
+    mg = _gpu()
+    N = 256
+    p = W.flower_mms(N)
+    s = _solver(mg, p, N, True, precision=1)
+    fresh = _solver(mg, p, N, True, precision=1)
+    ref_u, ref_h = fresh.solve(p.f, p.g, tol=1e-10)
+    for tol in (0.3, 0.1, 3e-2, 1e-3, 1e-6):
+        u, h = s.solve(p.f, p.g, tol=tol)
+        k = len(h) - 1
+        assert s.last_status == 0 and h[-1] <= tol * h[0] < h[-2]  # u = 0: h[0] is the norm of F
+        uf, hf = s.solve(p.f, p.g, tol=-1.0, max_cycles=k)
+        torch.cuda.synchronize()
+        assert np.array_equal(h, hf), tol
+        assert torch.equal(u, uf), tol
+        s.profile(True)
+        up, hp = s.solve(p.f, p.g, tol=tol)
+        s.profile(False)
+        assert np.array_equal(h, hp) and torch.equal(u, up), tol
+    u, h = s.solve(p.f, p.g, tol=1e-10)
+    assert np.array_equal(h, ref_h) and torch.equal(u, ref_u)
