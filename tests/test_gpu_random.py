@@ -1,0 +1,77 @@
+"""Seeded random problems against the oracle: domains (circles, rotated
+ellipses, flowers, noisy circles, some reaching the box sides), sizes
+N = coarsest_n 2^k with coarsest_n in {3, 4, 5, 12}, the smoothing counts,
+eta, the stabilisation rule, gamma, Galerkin or re-discretised coarse
+operators and, for a third of them, a straight Neumann part of the boundary.
+Iterates and residual histories after 3 cycles must agree to 1e-10 (relative
+to the largest entry), whether or not the method converges for the drawn
+parameters (re-discretised coarse operators on noisy boundaries can diverge,
+on both sides alike).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assembly as oasm
+from oracle import geometry as geo
+from oracle import multigrid as omg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_05105_amd as mg
+    return mg
+
+
+def _draw(trial):
+    rng = np.random.default_rng([2505, trial])
+    cn, k = [(4, 5), (4, 6), (4, 7), (3, 6), (3, 7), (5, 5), (5, 6), (12, 4)][rng.integers(8)]
+    N = cn * 2 ** k
+    kind = int(rng.integers(4))
+    cx, cy = rng.uniform(-0.3, 0.3, 2)
+    if kind == 0:
+        psi = W.circle(N, radius=rng.uniform(0.3, 1.2), center=(cx, cy))
+    elif kind == 1:
+        psi = W.ellipse(N, a=rng.uniform(0.3, 1.0), b=rng.uniform(0.2, 0.6), phi=rng.uniform(0, np.pi),
+                        center=(cx, cy))
+    elif kind == 2:
+        psi = W.flower(N, center=(cx, cy), r0=rng.uniform(0.4, 0.8), amp=rng.uniform(0.05, 0.2))
+    else:
+        psi = W.circle(N, radius=rng.uniform(0.5, 0.9), center=(cx, cy)) + 0.02 * rng.standard_normal((N + 1) ** 2)
+    chi = None
+    if trial % 3 == 2:  # Neumann where the rotated coordinate exceeds the centre's
+        phi = rng.uniform(0, 2 * np.pi)
+        x, y = W.grid_xy(N, W.BOX)
+        chi = np.cos(phi) * (x - cx) + np.sin(phi) * (y - cy)
+    params = dict(eta=int(rng.choice([0, 2, 4])), nu1=int(rng.integers(1, 3)), nu2=int(rng.integers(1, 3)),
+                  stab_rule=int(rng.choice([geo.STAB_PAPER, geo.STAB_LOCAL_EIG])),
+                  gamma=float(rng.choice([2.0, 3.0])), coarsest_n=cn, coarse_op=int(rng.integers(2)))
+    n = (N + 1) ** 2
+    data = rng.uniform(-1, 1, (3, n))
+    return N, psi, chi, params, data
+
+
+@pytest.mark.parametrize("trial", range(15))
+def test_random_problem_iterates(trial):
+    mg = _gpu()
+    N, psi, chi, p, (f, g, gN) = _draw(trial)
+    print(f"trial {trial}: N={N} neumann={chi is not None} {p}", flush=True)
+    kw = dict(gamma=p["gamma"], rule=p["stab_rule"])
+    if chi is not None:
+        kw["chi"] = chi
+    d = oasm.assemble(psi, N, **kw)
+    redisc = p["coarse_op"] == mg.COARSE_REDISCRETISED
+    H = omg.build_hierarchy(d, coarsest_n=p["coarsest_n"], rediscretise=(psi, dict(kw)) if redisc else None)
+    F = d.rhs(f, g, gN if chi is not None else None)
+    s = mg.Solver(psi, N, chi=chi, **p)
+    u, hist = s.solve(f, g, tol=-1.0, max_cycles=3, raise_on_fail=False, gN=gN if chi is not None else None)
+    ref = omg.solve(H, F, tol=-1.0, max_cycles=3, nu1=p["nu1"], nu2=p["nu2"], eta=p["eta"])
+    ug = u.cpu().numpy()
+    assert s.last_status in (0, mg._lib.ERR_DIVERGED)
+    assert len(hist) == len(ref.hist)
+    assert np.abs(ug - ref.u).max() <= 1e-10 * np.abs(ref.u).max()
+    assert np.abs(np.asarray(hist) - ref.hist).max() <= 1e-10 * ref.hist.max()
