@@ -6,12 +6,14 @@ operators and, for a third of them, a straight Neumann part of the boundary.
 Iterates and residual histories after 3 cycles must agree to 1e-10 (relative
 to the largest entry), whether or not the method converges for the drawn
 parameters (re-discretised coarse operators on noisy boundaries can diverge,
-on both sides alike).
+on both sides alike); where they converge, so must 3 transposed cycles and the
+gradients M lam, G^T lam and GN^T lam.
 """
 import numpy as np
 import pytest
 
 import workloads as W
+from oracle import adjoint as oadj
 from oracle import assembly as oasm
 from oracle import geometry as geo
 from oracle import multigrid as omg
@@ -75,3 +77,17 @@ def test_random_problem_iterates(trial):
     assert len(hist) == len(ref.hist)
     assert np.abs(ug - ref.u).max() <= 1e-10 * np.abs(ref.u).max()
     assert np.abs(np.asarray(hist) - ref.hist).max() <= 1e-10 * ref.hist.max()
+    if s.last_status != 0:
+        return
+    r = np.random.default_rng([2505, trial, 1]).standard_normal(d.n) * d.active
+    df, dg, lam, ah = s.adjoint(r, tol=-1.0, max_cycles=3)
+    aref = oadj.adjoint_solve(H, r, tol=-1.0, max_cycles=3, nu1=p["nu1"], nu2=p["nu2"], eta=p["eta"])
+    lam_o = aref.u
+    assert np.abs(lam.cpu().numpy() - lam_o).max() <= 1e-10 * np.abs(lam_o).max()
+    assert np.abs(np.asarray(ah) - aref.hist).max() <= 1e-10 * aref.hist.max()
+    mf, gg = oadj.gradients(d, lam_o)
+    assert np.abs(df.cpu().numpy() - mf).max() <= 1e-10 * np.abs(mf).max()
+    assert np.abs(dg.cpu().numpy() - gg).max() <= 1e-10 * np.abs(gg).max()
+    if chi is not None:
+        gn = oadj.neumann_gradient(d, lam_o)
+        assert np.abs(s.neumann_gradient(lam).cpu().numpy() - gn).max() <= 1e-10 * np.abs(gn).max()
