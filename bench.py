@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=3)
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint and further-form legs")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the solves, run a plain 512 MiB device copy (counter calibration)")
@@ -197,6 +197,85 @@ def bench_adjoint(args, mg, W, torch, dev):
             "cycles": k, "final_rel_residual": float(ha[-1] / ha[0]), "dtype": "f64"}
 
 
+def bench_next(args, mg, W, torch, dev, N=4096, oracle_N=1024, with_oracle=True):
+    """The further forms at N = 4096 (float64, tol as the main leg): the
+    W-cycle, the two-grid scheme, re-discretised coarse operators, the annulus
+    with a Neumann outer circle, and the global stabilisation parameter; each
+    with the oracle's time per cycle of the same form beside it, measured on a
+    bounded sample (N = 1024, two cycles after its set-up; skipped with the
+    CPU baseline)."""
+    import numpy as np
+    from oracle import assembly as oasm
+    from oracle import multigrid as omg
+    from oracle import geometry as ogeo
+    fl = W.flower_mms(N)
+    an = W.annulus_mms(N)
+    forms = [
+        ("w_cycle", fl, {"cycle": mg.CYCLE_W}),
+        ("two_grid", fl, {"cycle": mg.CYCLE_TWO_GRID}),
+        ("rediscretised", fl, {"coarse_op": mg.COARSE_REDISCRETISED}),
+        ("annulus_neumann", an, {}),
+        ("global_stab", fl, {"stab_rule": mg.STAB_GLOBAL}),
+    ]
+    out = {}
+    for name, prob, kw in forms:
+        t0 = time.perf_counter()
+        s = mg.Solver(prob.psi, N, chi=prob.chi, **kw)
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        f = torch.tensor(prob.f, device=dev)
+        g = torch.tensor(prob.g, device=dev)
+        gN = None if prob.gN is None else torch.tensor(prob.gN, device=dev)
+        u = torch.empty((N + 1) ** 2, dtype=torch.float64, device=dev)
+        cap = 100
+        s.solve(f, g, tol=args.tol, max_cycles=cap, out=u, gN=gN, raise_on_fail=False)
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, h = s.solve(f, g, tol=args.tol, max_cycles=cap, out=u, gN=gN, raise_on_fail=False)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        inf = s.info()
+        h = np.asarray(h)
+        cyc = len(h) - 1
+        rec = {"ms_per_solve": ms, "cycles": cyc, "converged": bool(s.last_status == 0),
+               "final_rel_residual": float(h[-1] / h[0]), "last_factor": float(h[-1] / h[-2]) if cyc else None,
+               "ms_per_cycle": ms / max(cyc, 1), "active_dof": inf["n_active"],
+               "value": inf["n_active"] / (ms * 1e-3) if s.last_status == 0 else None, "unit": "DOF/s",
+               "setup_ms": inf["setup_ms"], "setup_wall_ms": setup_ms, "dtype": "f64"}
+        if name == "global_stab":
+            rec["global_C_times_h"] = inf["global_C"] * 2.0 / N
+            rec["lanczos_steps"] = inf["global_iters"]
+        s.close()
+        out[name] = rec
+        log(f"[bench] next {name}: {ms:.2f} ms, {cyc} cycles")
+        if not with_oracle:
+            continue
+        # the oracle, the same form at N = oracle_N: set-up, then two cycles
+        po = W.flower_mms(oracle_N) if prob is fl else W.annulus_mms(oracle_N)
+        akw = {"chi": po.chi} if po.chi is not None else {}
+        t0 = time.perf_counter()
+        if name == "global_stab":
+            d = oasm.assemble(po.psi, oracle_N, rule=ogeo.STAB_GLOBAL, **akw)
+        else:
+            d = oasm.assemble(po.psi, oracle_N, **akw)
+        if name == "two_grid":
+            H = omg.two_grid(d)
+        elif name == "rediscretised":
+            H = omg.build_hierarchy(d, rediscretise=(po.psi, dict(akw)))
+        else:
+            H = omg.build_hierarchy(d)
+        t1 = time.perf_counter()
+        F = d.rhs(po.f, po.g, po.gN)
+        omg.solve(H, F, tol=-1.0, max_cycles=2, gamma_star=2 if name == "w_cycle" else 1)
+        t2 = time.perf_counter()
+        rec["oracle"] = {"N": oracle_N, "setup_s": t1 - t0, "per_cycle_s": (t2 - t1) / 2, "cores": 1,
+                         "kind": "oracle", "sample": f"N={oracle_N}: set-up, then 2 cycles"}
+        log(f"[bench] next {name}: oracle {(t2 - t1) / 2:.2f} s/cycle at N={oracle_N}")
+    return out
+
+
 def _cpu_name():
     try:
         for line in open("/proc/cpuinfo"):
@@ -309,6 +388,7 @@ def main():
         s64.close()
         out["batched"] = bench_batched(args, mg, W, torch, dev)
         out["adjoint"] = bench_adjoint(args, mg, W, torch, dev)
+        out["next"] = bench_next(args, mg, W, torch, dev, with_oracle=not args.no_cpu_baseline)
 
     if args.copy_probe:
         # a plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for it calibrates the counters
