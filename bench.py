@@ -276,6 +276,20 @@ def bench_next(args, mg, W, torch, dev, N=4096, oracle_N=1024, with_oracle=True)
     return out
 
 
+def _one_thread():
+    """The oracle timings run on one core: BLAS/OpenMP pools limited to one
+    thread (scipy's sparse products are single-threaded anyway)."""
+    try:
+        import numpy  # noqa: F401  (load the pools first: only loaded ones are limited)
+        import scipy.linalg  # noqa: F401
+        import scipy.sparse.linalg  # noqa: F401
+        from threadpoolctl import threadpool_limits
+        return threadpool_limits(limits=1)
+    except ImportError:  # no pools to limit
+        import contextlib
+        return contextlib.nullcontext()
+
+
 def _cpu_name():
     try:
         for line in open("/proc/cpuinfo"):
@@ -388,7 +402,8 @@ def main():
         s64.close()
         out["batched"] = bench_batched(args, mg, W, torch, dev)
         out["adjoint"] = bench_adjoint(args, mg, W, torch, dev)
-        out["next"] = bench_next(args, mg, W, torch, dev, with_oracle=not args.no_cpu_baseline)
+        with _one_thread():
+            out["next"] = bench_next(args, mg, W, torch, dev, with_oracle=not args.no_cpu_baseline)
 
     if args.copy_probe:
         # a plain copy of known size: what FETCH_SIZE / WRITE_SIZE read for it calibrates the counters
@@ -403,7 +418,8 @@ def main():
 
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(prob, N, cycles, args.cpu_cycles)
+        with _one_thread():
+            out["cpu_baseline"] = cpu_baseline(prob, N, cycles, args.cpu_cycles)
         hc = np.array(out["cpu_baseline"].pop("hist"))
         k = len(hc)
         out["cpu_baseline"]["hist_rel_diff_vs_gpu"] = float(
