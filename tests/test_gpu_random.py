@@ -7,7 +7,8 @@ Iterates and residual histories after 3 cycles must agree to 1e-10 (relative
 to the largest entry), whether or not the method converges for the drawn
 parameters (re-discretised coarse operators on noisy boundaries can diverge,
 on both sides alike); where they converge, so must 3 transposed cycles and the
-gradients M lam, G^T lam and GN^T lam.
+gradients M lam, G^T lam and GN^T lam, and the mixed form must reach the
+float64 tolerance at the float64 solution (1e-8).
 """
 import numpy as np
 import pytest
@@ -91,3 +92,11 @@ def test_random_problem_iterates(trial):
     if chi is not None:
         gn = oadj.neumann_gradient(d, lam_o)
         assert np.abs(s.neumann_gradient(lam).cpu().numpy() - gn).max() <= 1e-10 * np.abs(gn).max()
+    gNk = gN if chi is not None else None
+    u64, h64 = s.solve(f, g, tol=1e-10, max_cycles=200, raise_on_fail=False, gN=gNk)
+    if s.last_status != 0:  # converges too slowly for the cap: nothing to compare
+        return
+    sm = mg.Solver(psi, N, chi=chi, precision=mg.PREC_MIXED, **p)
+    um, hm = sm.solve(f, g, tol=1e-10, max_cycles=200, gN=gNk)
+    assert hm[-1] <= 1e-10 * hm[0]
+    assert torch.abs(um - u64).max() <= 1e-8 * torch.abs(u64).max()
