@@ -44,15 +44,17 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(domain="flower", N=4096):
     """HBM bytes per launch of the sweep kernel from the committed counter runs,
-    or None when they were taken on other sources."""
+    or None when they were taken on other sources or another workload."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     if t.get("source_hash") != source_hash():
+        return None
+    if t.get("workload") != {"domain": domain, "N": N}:
         return None
     return t.get("bytes_per_launch")
 
@@ -356,7 +358,7 @@ def main():
     avg_ms = prof["total_ms"] / max(prof["launches"], 1)
     alg = prof["alg_bytes"] / max(prof["launches"], 1)
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.domain, N)
     log(f"[bench] {SWEEP_KERNEL}: {prof['launches']} launches, avg {avg_ms * 1e3:.2f} us, "
         f"{alg / 1e6:.1f} MB algorithmic -> {achieved:.0f} GB/s")
 

@@ -28,7 +28,16 @@ def test_committed_counters_match_the_sources():
     with open(bench.TRAFFIC_FILE) as fh:
         t = json.load(fh)
     assert t["kernel"] == bench.SWEEP_KERNEL
-    assert bench.measured_traffic() == (t["bytes_per_launch"] if t["source_hash"] == bench.source_hash() else None)
+    assert bench.measured_traffic("flower", 4096) == (
+        t["bytes_per_launch"] if t["source_hash"] == bench.source_hash() else None)
+
+
+def test_counters_of_another_workload_give_no_traffic():
+    with open(bench.TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    assert t["workload"] == {"domain": "flower", "N": 4096}
+    assert bench.measured_traffic("flower", 16384) is None
+    assert bench.measured_traffic("ellipse", 4096) is None
 
 
 def test_stale_counters_give_no_traffic(monkeypatch, tmp_path):
