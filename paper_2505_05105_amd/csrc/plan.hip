@@ -11,6 +11,7 @@
 //    right-hand side, residual on the bounding box grown by one ring, the
 //    stored stencil rows and the cut lists) fit in one workgroup's LDS.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_map>
 
@@ -179,6 +180,10 @@ int build_plans(mgfem_ctx* c) {
   const size_t cap = (size_t)lds_max - 4096;  // room for the kernels' static LDS
   // --- cut positions, snapshots and cut groups, every level with smoothing
   const int D = 4 * c->p.eta;
+  // MGFEM_NO_CUT_GROUPS=1: no group plans, so every level takes the list
+  // smoother (the path of a level whose groups do not fit in LDS)
+  const char* ng_env = std::getenv("MGFEM_NO_CUT_GROUPS");
+  const bool no_groups = ng_env && ng_env[0] && ng_env[0] != '0';
   for (int l = 0; l + 1 < nl; ++l) {
     Level& L = c->lv[l];
     const int cnt = L.cut_off[4];
@@ -190,7 +195,7 @@ int build_plans(mgfem_ctx* c) {
     MGFEM_HIP_TRY(ctx_alloc_t(c, &L.snap, std::max(1, cnt)));
     if (mixed) MGFEM_HIP_TRY(ctx_alloc_t(c, &L.snap32, std::max(1, cnt)));
     MGFEM_HIP_TRY(hipGetLastError());
-    if (cnt == 0 || c->p.eta == 0) continue;
+    if (cnt == 0 || c->p.eta == 0 || no_groups) continue;
     std::vector<int> nodes(cnt);
     MGFEM_HIP_TRY(hipMemcpyAsync(nodes.data(), L.cut_list, cnt * sizeof(int), hipMemcpyDeviceToHost, c->s));
     MGFEM_HIP_TRY(hipStreamSynchronize(c->s));

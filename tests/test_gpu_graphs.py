@@ -123,3 +123,40 @@ def test_mixed_loop_queued_iteration_is_discarded():
         assert np.array_equal(h, hp) and torch.equal(u, up), tol
     u, h = s.solve(p.f, p.g, tol=1e-10)
     assert np.array_equal(h, ref_h) and torch.equal(u, ref_u)
+
+
+def test_list_smoother_without_group_plans():
+    """MGFEM_NO_CUT_GROUPS=1 at set-up: the extra smoothing runs as one launch
+    per colour over the cut-vertex list (the path of a level whose groups do
+    not fit in LDS) instead of the grouped kernel.  Same cycles up to
+    rounding (1/a_ii multiplied there, divided here), both against the oracle,
+    eager and replayed, float64 and mixed."""
+    mg = _gpu()
+    from oracle import assembly as oasm
+    from oracle import multigrid as omg
+    N = 256
+    p = W.flower_mms(N)
+    d = oasm.assemble(p.psi, N)
+    ref = omg.solve(omg.build_hierarchy(d), d.rhs(p.f, p.g), tol=-1.0, max_cycles=3)
+    old = os.environ.get("MGFEM_NO_CUT_GROUPS")
+    os.environ["MGFEM_NO_CUT_GROUPS"] = "1"
+    try:
+        sl = _solver(mg, p, N, True)
+        sle = _solver(mg, p, N, False)
+        slm = _solver(mg, p, N, True, precision=1)
+    finally:
+        if old is None:
+            del os.environ["MGFEM_NO_CUT_GROUPS"]
+        else:
+            os.environ["MGFEM_NO_CUT_GROUPS"] = old
+    sg = _solver(mg, p, N, True)
+    for s in (sl, sle, sg):
+        u, h = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
+        assert np.abs(u.cpu().numpy() - ref.u).max() <= 1e-10 * np.abs(ref.u).max()
+    ul, hl = sl.solve(p.f, p.g, tol=1e-10)
+    ug, hg = sg.solve(p.f, p.g, tol=1e-10)
+    ule, hle = sle.solve(p.f, p.g, tol=1e-10)
+    assert len(hl) == len(hg) and np.array_equal(hl, hle) and torch.equal(ul, ule)
+    assert torch.abs(ul - ug).max() <= 1e-10 * torch.abs(ug).max()
+    um, hm = slm.solve(p.f, p.g, tol=1e-10)
+    assert slm.last_status == 0 and torch.abs(um - ug).max() <= 1e-8 * torch.abs(ug).max()
