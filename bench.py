@@ -278,6 +278,12 @@ def bench_next(args, mg, W, torch, dev, N=4096, oracle_N=1024, with_oracle=True)
     return out
 
 
+def _final_l2(solver):
+    """||F - A u||_2 / ||F||_2 after the solver's last solve (it recorded it)."""
+    l2 = solver.residual_l2()
+    return float(l2[-1] / l2[0]) if len(l2) else None
+
+
 def _one_thread():
     """The oracle timings run on one core: BLAS/OpenMP pools limited to one
     thread (scipy's sparse products are single-threaded anyway)."""
@@ -373,6 +379,7 @@ def main():
         "grid_nodes_per_s": (N + 1) ** 2 / (ms * 1e-3),
         "setup_ms": info["setup_ms"],
         "final_rel_residual": float(hist[-1] / hist[0]),
+        "final_rel_residual_l2": _final_l2(s64),
         "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": alg,

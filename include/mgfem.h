@@ -267,6 +267,19 @@ int32_t mgfem_level_n(mgfem_handle h, int32_t level);
 int mgfem_smooth(mgfem_handle h, int32_t level, double* x_dev, const double* b_dev,
                  int32_t steps, int32_t reverse);
 
+/*
+ * The Euclidean residual norms ||F - A u_m||_2, m = 0..cycles, of the last
+ * mgfem_solve, mgfem_solve_mixed_bc or mgfem_adjoint on this handle, beside
+ * the max-norm history those calls return (section 3.1 measures convergence
+ * in the max norm; the l2 norm is reported with it).
+ *  l2_hist_host : host, room for `capacity` float64 (may be NULL when
+ *                 capacity is 0); receives the first min(capacity, count).
+ *  count        : host, receives the number of entries of that history (may
+ *                 be NULL).
+ * Returns INVALID_ARG for a NULL handle or a negative capacity.
+ */
+int mgfem_residual_l2(mgfem_handle h, double* l2_hist_host, int32_t capacity, int32_t* count);
+
 /* Per-level row counts: active rows, rows whose stencil is read from the
  * stored planes (the others are the interior Q1 stencil), extra-smoothing
  * vertices.  Any output pointer may be NULL. */

@@ -73,6 +73,16 @@ class Solver:
         out["n_cells_by_type"] = dict(zip(CELL_TYPES, list(inf.n_cells_by_type)))
         return out
 
+    def residual_l2(self):
+        """||F - A u_m||_2, m = 0..cycles, of the last solve or adjoint."""
+        cnt = C.c_int32(0)
+        _lib.check(_lib.lib().mgfem_residual_l2(self.handle, None, 0, C.byref(cnt)), self.handle)
+        out = np.zeros(cnt.value)
+        if cnt.value:
+            _lib.check(_lib.lib().mgfem_residual_l2(self.handle, out.ctypes.data_as(C.POINTER(C.c_double)),
+                                                    cnt.value, C.byref(cnt)), self.handle)
+        return out
+
     def level_n(self, level):
         return _lib.lib().mgfem_level_n(self.handle, level)
 

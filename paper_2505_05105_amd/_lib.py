@@ -27,7 +27,7 @@ EXPORTED = (
     "mgfem_query", "mgfem_export", "mgfem_level_n", "mgfem_smooth", "mgfem_destroy",
     "mgfem_status_string", "mgfem_last_error", "mgfem_setup_batched", "mgfem_solve_batched",
     "mgfem_level_counts", "mgfem_profile", "mgfem_profile_read", "mgfem_batched_tile",
-    "mgfem_setup_mixed_bc", "mgfem_solve_mixed_bc", "mgfem_adjoint_neumann",
+    "mgfem_setup_mixed_bc", "mgfem_solve_mixed_bc", "mgfem_adjoint_neumann", "mgfem_residual_l2",
 )
 
 
@@ -89,6 +89,7 @@ def lib():
         "mgfem_profile": (C.c_int, [P, I32]),
         "mgfem_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP, DP]),
         "mgfem_batched_tile": (C.c_int, [P]),
+        "mgfem_residual_l2": (C.c_int, [P, DP, I32, C.POINTER(I32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -568,7 +568,8 @@ int run_iteration(mgfem_ctx* c, const IterKind& k, const GraphEntry** used) {
 int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cycles, bool reverse,
             bool mixed, bool warm, double bnorm, double* hist, int* ncyc) {
   Level& L0 = c->lv[0];
-  double dummy, r0, l2;
+  double r0, l2, l2F = c->f_l2;
+  c->l2_hist.clear();
   L0.X[0] = c->x0;
   L0.b = const_cast<double*>(b);
   L0.cur = 0;
@@ -577,9 +578,10 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   int rc;
   if (bnorm < 0.0) {
     launch_residual_norm(c, b, c->zero, nullptr);
-    rc = read_norm(c, bnorm, dummy);
+    rc = read_norm(c, bnorm, l2F);
     if (rc) return rc;
   }
+  l2 = l2F;  // u = 0: the residual is F
   if (mixed) {
     // r = F - A u, its float copy and the zero float start iterate
     launch_outer(c, c->x0, nullptr, nullptr, L0.b32, L0.X32[0]);
@@ -593,6 +595,7 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     r0 = bnorm;  // u = 0
   }
   if (hist) hist[0] = r0;
+  c->l2_hist.push_back(l2);
   if (!mixed) gather_snap(c, 0, false);
   double prev = r0;
   int grow = 0, m = 0;
@@ -658,6 +661,7 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     --queued;
     ++m;
     if (hist) hist[m] = rm;
+    c->l2_hist.push_back(l2);
     if (!std::isfinite(rm)) {
       status = MGFEM_ERR_DIVERGED;
       break;
@@ -861,6 +865,7 @@ int mgfem_solve_mixed_bc(mgfem_handle c, const double* f_dev, const double* gD_d
   double bnorm, l2;
   int rc = read_norm(c, bnorm, l2);
   if (rc) return rc;
+  c->f_l2 = l2;
   int nc = 0;
   rc = iterate(c, u_dev, c->F, rel_tol, max_cycles, false, c->p.precision == MGFEM_PREC_MIXED, warm, bnorm,
                res_hist_host, &nc);
@@ -934,6 +939,14 @@ int mgfem_smooth(mgfem_handle c, int32_t level, double* x_dev, const double* b_d
   L.cur = 0;
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return MGFEM_OK;
+}
+
+int mgfem_residual_l2(mgfem_handle c, double* l2_hist_host, int32_t capacity, int32_t* count) {
+  if (!c || capacity < 0 || (capacity > 0 && !l2_hist_host)) return MGFEM_ERR_INVALID_ARG;
+  const int n = std::min(capacity, (int)c->l2_hist.size());
+  for (int m = 0; m < n; ++m) l2_hist_host[m] = c->l2_hist[m];
+  if (count) *count = (int32_t)c->l2_hist.size();
   return MGFEM_OK;
 }
 

@@ -263,6 +263,8 @@ struct mgfem_ctx {
   std::map<std::vector<int>, mgfem::GraphEntry> graphs;
   double* x0 = nullptr;             // level-0 iterate owned by the library (ping-pong partner of lv[0].X[1])
   int u_cur = 0;                    // mixed precision: which level-0 float64 buffer holds u
+  double f_l2 = 0.0;                // ||F||_2 of the right-hand side the last solve assembled
+  std::vector<double> l2_hist;      // ||F - A u_m||_2 of the last solve or adjoint, m = 0..cycles
   std::string last_error;
   bool batched_member = false;
   std::vector<mgfem_ctx*> members;  // batched handle: one context per problem

@@ -14,7 +14,7 @@ LIB = os.path.join(ROOT, "paper_2505_05105_amd", "libmgfem.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mgfem_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(mgfem_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")

@@ -312,3 +312,30 @@ def test_error_paths():
     else:
         u, hist = bad.solve(p.f, p.g, tol=1e-10, max_cycles=40, raise_on_fail=False)
         assert bad.last_status in (mg._lib.ERR_DIVERGED, mg._lib.ERR_NOT_CONVERGED)
+
+
+def test_residual_l2_history_matches_oracle():
+    """The l2 residual norms beside the max-norm history (section 3.1 uses
+    the max norm; both are recorded), float64 forward, adjoint and mixed."""
+    mg = _gpu()
+    N = 128
+    p = W.flower_mms(N)
+    d = oasm.assemble(p.psi, N)
+    H = omg.build_hierarchy(d)
+    F = d.rhs(p.f, p.g)
+    s = mg.Solver(p.psi, N)
+    u, hist = s.solve(p.f, p.g, tol=1e-10)
+    ref = omg.solve(H, F, tol=1e-10)
+    l2 = s.residual_l2()
+    assert len(l2) == len(hist) == len(ref.hist_l2)
+    np.testing.assert_allclose(l2, ref.hist_l2, rtol=1e-8, atol=50 * 2.2e-16 * ref.hist_l2[0])
+    r = np.random.default_rng(2).standard_normal(d.n) * d.active
+    _, _, lam, ah = s.adjoint(r, tol=-1.0, max_cycles=3)
+    from oracle import adjoint as oadj
+    aref = oadj.adjoint_solve(H, r, tol=-1.0, max_cycles=3)
+    np.testing.assert_allclose(s.residual_l2(), aref.hist_l2, rtol=1e-8)
+    sm = mg.Solver(p.psi, N, precision=mg.PREC_MIXED)
+    um, hm = sm.solve(p.f, p.g, tol=1e-10)
+    l2m = sm.residual_l2()
+    assert len(l2m) == len(hm) and l2m[0] == pytest.approx(ref.hist_l2[0], rel=1e-12)
+    assert l2m[-1] <= 1e-9 * l2m[0]
