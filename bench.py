@@ -400,10 +400,28 @@ def main():
         t1 = time.perf_counter()
         msm = (t1 - t0) * 1e3 / args.steps
         err = float((um - u).abs().max() / u.abs().max())
+        # the float32 finest sweep timed the same way (events around each launch)
+        smx.profile(True)
+        run(smx, um)
+        torch.cuda.synchronize()
+        smx.profile(True)
+        for _ in range(args.steps):
+            run(smx, um)
+        torch.cuda.synchronize()
+        pm = smx.profile_read(1)
+        smx.profile(False)
+        avg32 = pm["total_ms"] / max(pm["launches"], 1)
+        alg32 = pm["alg_bytes"] / max(pm["launches"], 1)
+        ach32 = alg32 / (avg32 * 1e-3) / 1e9 if pm["launches"] else 0.0
         out["mixed"] = {"value": dof / (msm * 1e-3), "unit": "DOF/s", "ms_per_step": msm,
                         "cycles": len(hm) - 1, "dtype": "f32 cycles / f64 outer",
                         "rel_err_vs_fp64": err, "final_rel_residual": float(hm[-1] / hm[0]),
-                        "speedup_vs_fp64": ms / msm}
+                        "speedup_vs_fp64": ms / msm,
+                        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL.replace("double", "float"),
+                                     "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": ach32 / HBM_PEAK_GBS, "traffic": None,
+                                     "avg_launch_us": avg32 * 1e3, "alg_bytes_per_launch": alg32,
+                                     "launches": pm["launches"]}}
         log(f"[bench] mixed: {msm:.3f} ms/solve, {len(hm) - 1} cycles, err vs fp64 {err:.2e}")
         smx.close()
 

@@ -291,10 +291,11 @@ int mgfem_level_counts(mgfem_handle h, int32_t level, int64_t* n_active, int64_t
  * every launch of the profiled kernel class is bracketed by HIP events on the
  * handle's stream; after each solve the durations, the launch count and the
  * algorithmic bytes of those launches are accumulated.  Class 0 is the
- * float64 full-sweep kernel of the finest level;
- * its algorithmic bytes per launch are 25 per active row (iterate read and
- * written, right-hand side, flag byte) plus 72 per stored row, plus 8 per
- * active coarse row when the sweep applies the prolongation.
+ * float64 full-sweep kernel of the finest level, class 1 the float32 one of
+ * the mixed-precision cycles; the algorithmic bytes per launch are, with w
+ * the value size (8 or 4), 3w + 1 per active row (iterate read and written,
+ * right-hand side, flag byte) plus 9w per stored row, plus w per active
+ * coarse row when the sweep applies the prolongation.
  * mgfem_profile resets the counters.
  */
 int mgfem_profile(mgfem_handle h, int32_t enable);

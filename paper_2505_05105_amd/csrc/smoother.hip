@@ -1080,12 +1080,14 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   a.tc_idx = L.tc_idx;
   a.tc_pos = L.tc_pos;
   a.zero = reinterpret_cast<const T*>(c->zero);
-  if (c->prof.on && std::is_same<T, double>::value && l == 0) {
+  if (c->prof.on && l == 0) {
     // algorithmic bytes: per active row x read and written, b read, its flag,
-    // the 72 bytes of a stored row; a fused prolongation also reads x_c
-    double bytes = 25.0 * L.n_active + 72.0 * L.n_stored;
-    if (prolong_from) bytes += 8.0 * c->lv[l + 1].n_active;
-    prof_launch(c, 0, bytes, [a](hipStream_t st) {
+    // the nine coefficients of a stored row; a fused prolongation also reads
+    // x_c (class 0 float64, class 1 the float32 sweeps of the mixed solve)
+    constexpr double vb = (double)sizeof(T);
+    double bytes = (3.0 * vb + 1.0) * L.n_active + 9.0 * vb * L.n_stored;
+    if (prolong_from) bytes += vb * c->lv[l + 1].n_active;
+    prof_launch(c, std::is_same<T, double>::value ? 0 : 1, bytes, [a](hipStream_t st) {
       hipLaunchKernelGGL((k_sweep<T, TW, TH, BS>), dim3(8 * a.per), dim3(BS), 0, st, a);
     });
   } else {

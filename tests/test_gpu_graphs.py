@@ -160,3 +160,21 @@ def test_list_smoother_without_group_plans():
     assert torch.abs(ul - ug).max() <= 1e-10 * torch.abs(ug).max()
     um, hm = slm.solve(p.f, p.g, tol=1e-10)
     assert slm.last_status == 0 and torch.abs(um - ug).max() <= 1e-8 * torch.abs(ug).max()
+
+
+def test_profiled_mixed_replay_times_the_float_sweep():
+    """Class 1: the float32 finest sweeps of the mixed cycles, three per
+    outer iteration; the profiled solve equals the unprofiled one."""
+    mg = _gpu()
+    N = 2048
+    p = W.flower_mms(N)
+    s = mg.Solver(p.psi, N, precision=mg.PREC_MIXED)
+    u0, h0 = s.solve(p.f, p.g, tol=1e-10)
+    s.profile(True)
+    u1, h1 = s.solve(p.f, p.g, tol=1e-10)
+    prof = s.profile_read(1)
+    assert s.profile_read(0)["launches"] == 0
+    s.profile(False)
+    assert np.array_equal(h0, h1) and torch.equal(u0, u1)
+    assert prof["launches"] == 3 * (len(h1) - 1)
+    assert prof["total_ms"] > 0 and prof["alg_bytes"] > 0
