@@ -7,8 +7,14 @@ and adjoint runs in the library's HIP kernels (see include/mgfem.h).
     u, hist = solver.solve(f, g, tol=1e-10)  # u: torch float64 on the GPU
     u = GhostFEMSolve.apply(f, g, solver)    # differentiable in f and g
 
+    l2 = solver.residual_l2()                # ||F - A u_m||_2 beside the max-norm hist
+
     solver = Solver(psi, N, chi=chi)         # Neumann where chi > 0 (mixed boundaries)
     u, hist = solver.solve(f, gD, gN=gN)
+    u = GhostFEMSolveMixed.apply(f, gD, gN, solver)   # differentiable in f, g_D and g_N
+
+    batch = BatchedSolver(psis, Ns)          # many problems, one persistent launch
+    us, hists = batch.solve(fs, gs, tol=1e-10)
 """
 from __future__ import annotations
 
