@@ -137,3 +137,57 @@ def test_constant_scales_as_inverse_h():
     assert geo.stabilization_constant(psi4, h=0.5) == pytest.approx(2 * geo.stabilization_constant(psi4, h=1.0))
     assert geo.stabilization_constant(psi4, h=0.5, rule=geo.STAB_LOCAL_EIG) == \
         pytest.approx(geo.stabilization_constant(psi4, h=0.5), rel=1e-9)
+
+
+def saddle_psi(rng, split):
+    """A saddle cell: v0 and v2 inside, v1 and v3 outside; the mean of the
+    four values decides between two triangles (>= 0) and one hexagon (< 0)."""
+    while True:
+        a, c = -rng.uniform(0.05, 2.0, size=2)
+        b, d = rng.uniform(0.05, 2.0, size=2)
+        if (a + b + c + d >= 0.0) == split:
+            return np.array([a, b, c, d])
+
+
+def _own_segment(poly, segs):
+    """The interface segment whose two end points are vertices of poly."""
+    for P, Q in segs:
+        if all(np.min(np.abs(poly - X).sum(axis=1)) < 1e-14 for X in (P, Q)):
+            return P, Q
+    raise AssertionError("no segment belongs to this polygon")
+
+
+def test_split_saddle_constant_is_the_larger_triangle_eigenvalue():
+    # reading of saddle cells: split into two triangles, C = max of the two
+    # triangle constants; each is checked against the local generalised
+    # eigenproblem of section 5.2 posed on that triangle alone, and the
+    # eigenproblem of the whole cell (both pieces) stays below it, so
+    # lambda_K = gamma C keeps the coercivity bound lambda_K > C_K
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        psi4 = saddle_psi(rng, split=True)
+        t, polys, segs, _ = geo.cut_geometry(psi4)
+        assert t == geo.SADDLE_SPLIT and len(polys) == 2 and len(segs) == 2
+        each = [asm.local_eigen_constant([p], [_own_segment(p, segs)]) for p in polys]
+        C = geo.stabilization_constant(psi4)
+        assert C == pytest.approx(max(each), rel=1e-9)
+        assert C > min(each) or each[0] == pytest.approx(each[1], rel=1e-9)
+        assert asm.local_eigen_constant(polys, segs) <= C * (1 + 1e-12)
+        for h in (0.5, 2.0 / 256):
+            assert geo.stabilization_constant(psi4, h=h) == pytest.approx(C / h, rel=1e-13)
+
+
+def test_hexagon_saddle_value_bounds_its_eigenvalue():
+    # reading of joined saddle cells: a hexagon takes the pentagon value
+    # 3 sqrt(2)/h, which must bound the hexagon's own local eigenvalue
+    rng = np.random.default_rng(12)
+    for _ in range(40):
+        psi4 = saddle_psi(rng, split=False)
+        t, polys, segs, _ = geo.cut_geometry(psi4)
+        assert t == geo.SADDLE_HEX and len(polys) == 1 and len(polys[0]) == 6
+        C = geo.stabilization_constant(psi4)
+        assert C == pytest.approx(3 * math.sqrt(2), rel=1e-15)
+        assert asm.local_eigen_constant(polys, segs) <= C * (1 + 1e-12)
+        # the rule the product also offers: the local eigenproblem itself
+        assert geo.stabilization_constant(psi4, rule=geo.STAB_LOCAL_EIG) == \
+            pytest.approx(asm.local_eigen_constant(polys, segs), rel=1e-12)

@@ -180,3 +180,64 @@ def test_rediscretised_hierarchy_solves_the_fine_problem():
     u = np.zeros(d.n)
     u[a] = spla.spsolve(d.A[a][:, a].tocsc(), F[a])
     assert np.abs(res.u - u).max() <= 1e-9 * np.abs(u).max()
+
+
+def _brute_coarse_cut(fine_cut_cells, Nf):
+    """Coarse cells (ci, cj) of an Nf/2 grid that contain a listed fine cell:
+    fine cell (i, j) lies in coarse cell (i // 2, j // 2)."""
+    return {(i // 2, j // 2) for i, j in fine_cut_cells}
+
+
+def _brute_vertices(cells):
+    return {(ci + di, cj + dj) for ci, cj in cells for di in (0, 1) for dj in (0, 1)}
+
+
+@pytest.mark.parametrize("pattern", ["single", "diagonal_pair", "ring", "corner_block", "odd_row"])
+def test_coarse_extra_smoothing_set_on_hand_built_patterns(pattern):
+    # reading of section 5.3's extra smoothing on coarse grids: a coarse cell
+    # is cut when it contains a fine cut cell (OR over its four sub-cells,
+    # at sub-cell offsets (0,0), (1,0), (0,1), (1,1)); the extra-smoothing
+    # nodes are the vertices of the cut cells.  Patterns on an 8 x 8 grid,
+    # expected sets by enumeration.
+    Nf = 8
+    cells = {
+        "single": [(5, 2)],
+        "diagonal_pair": [(1, 1), (2, 2)],
+        "ring": [(i, j) for i in range(Nf) for j in range(Nf) if i in (0, Nf - 1) or j in (0, Nf - 1)],
+        "corner_block": [(6, 6), (7, 6), (6, 7), (7, 7)],
+        "odd_row": [(i, 3) for i in range(1, Nf, 2)],
+    }[pattern]
+    mask = np.zeros(Nf * Nf, dtype=bool)
+    for i, j in cells:
+        mask[i + j * Nf] = True  # cell index i + j N (section 5.1's single index)
+    coarse = mg.coarsen_cut_cells(mask, Nf)
+    Nc = Nf // 2
+    got = {(q % Nc, q // Nc) for q in np.nonzero(coarse)[0]}
+    assert got == _brute_coarse_cut(cells, Nf)
+    # vertex sets on both grids
+    vf = mg.cut_vertex_mask(mask, Nf)
+    assert {(k % (Nf + 1), k // (Nf + 1)) for k in np.nonzero(vf)[0]} == _brute_vertices(cells)
+    vc = mg.cut_vertex_mask(coarse, Nc)
+    assert {(k % (Nc + 1), k // (Nc + 1)) for k in np.nonzero(vc)[0]} == _brute_vertices(got)
+    # and one level further down
+    cc = mg.coarsen_cut_cells(coarse, Nc)
+    assert {(q % 2, q // 2) for q in np.nonzero(cc)[0]} == _brute_coarse_cut(got, Nc)
+
+
+def test_hierarchy_cut_sets_follow_the_fine_cut_cells(flower64):
+    # every level's extra-smoothing mask equals the active vertices of the
+    # coarse cells that contain a fine cut cell of the assembled problem,
+    # counted from the fine cell types by enumeration
+    d, H = flower64
+    N = d.N
+    t = d.cell_type
+    fine = [(q % N, q // N) for q in range(N * N) if t[q] not in (0, 4)]
+    cells, n = fine, N
+    for lv in H.levels[:-1]:
+        assert lv.N == n
+        expect = np.zeros((n + 1) ** 2, dtype=bool)
+        for i, j in _brute_vertices(cells):
+            expect[i + j * (n + 1)] = True
+        np.testing.assert_array_equal(lv.cut, expect & lv.active)
+        cells, n = sorted(_brute_coarse_cut(cells, n)), n // 2
+    assert H.levels[-1].cut is None  # no extra smoothing on the coarsest grid
