@@ -839,6 +839,17 @@ int global_constant(const double* psi, const double* chi, int32_t N, const mgfem
   return MGFEM_OK;
 }
 
+// The calls of one problem need a handle made by mgfem_setup or
+// mgfem_setup_mixed_bc: a batched handle has no levels of its own (its
+// problems live in member contexts), and a member context is reached only
+// through mgfem_solve_batched.
+int single_problem_check(mgfem_ctx* c) {
+  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (c->batched_member || !c->members.empty() || c->lv.empty())
+    return fail(c, MGFEM_ERR_INVALID_ARG, "batched handle: use mgfem_solve_batched");
+  return MGFEM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -854,8 +865,7 @@ int mgfem_solve_mixed_bc(mgfem_handle c, const double* f_dev, const double* gD_d
                          double rel_tol, int32_t max_cycles, uint32_t flags, double* u_dev,
                          double* res_hist_host, int32_t* n_cycles) {
   const double* g_dev = gD_dev;
-  if (!c) return MGFEM_ERR_INVALID_ARG;
-  if (c->batched_member) return fail(c, MGFEM_ERR_INVALID_ARG, "batched handle: use mgfem_solve_batched");
+  if (const int e = single_problem_check(c)) return e;
   if (!f_dev || !g_dev || !u_dev || max_cycles < 0)
     return fail(c, MGFEM_ERR_INVALID_ARG, "f, g and u must be device pointers; max_cycles >= 0");
   const bool warm = (flags & MGFEM_SOLVE_WARM_START) != 0;
@@ -876,7 +886,7 @@ int mgfem_solve_mixed_bc(mgfem_handle c, const double* f_dev, const double* gD_d
 int mgfem_adjoint(mgfem_handle c, const double* dJdu_dev, double rel_tol, int32_t max_cycles,
                   double* lam_dev, double* dJdf_dev, double* dJdg_dev, double* res_hist_host,
                   int32_t* n_cycles) {
-  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (const int e = single_problem_check(c)) return e;
   if (!dJdu_dev || max_cycles < 0) return fail(c, MGFEM_ERR_INVALID_ARG, "dJdu must be a device pointer");
   double* lam = lam_dev ? lam_dev : c->lam;
   // the adjoint right-hand side must vanish off the active nodes
@@ -894,8 +904,7 @@ int mgfem_adjoint(mgfem_handle c, const double* dJdu_dev, double rel_tol, int32_
 }
 
 int mgfem_adjoint_neumann(mgfem_handle c, const double* lam_dev, double* dJdgN_dev) {
-  if (!c) return MGFEM_ERR_INVALID_ARG;
-  if (c->batched_member) return fail(c, MGFEM_ERR_INVALID_ARG, "batched handle");
+  if (const int e = single_problem_check(c)) return e;
   if (!lam_dev || !dJdgN_dev) return fail(c, MGFEM_ERR_INVALID_ARG, "lam and dJdgN must be device pointers");
   launch_gn_apply(c, lam_dev, dJdgN_dev);  // GN^T = GN
   MGFEM_HIP_TRY(hipGetLastError());
@@ -905,7 +914,7 @@ int mgfem_adjoint_neumann(mgfem_handle c, const double* lam_dev, double* dJdgN_d
 
 int mgfem_misfit(mgfem_handle c, const double* u_dev, const double* ut_dev, double* J_host,
                  double* dJdu_dev) {
-  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (const int e = single_problem_check(c)) return e;
   if (!u_dev || !ut_dev || !J_host) return fail(c, MGFEM_ERR_INVALID_ARG, "u, ut and J must be given");
   double* e = c->F64tmp;
   double* Me = dJdu_dev ? dJdu_dev : c->lam;

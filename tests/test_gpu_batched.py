@@ -55,3 +55,37 @@ def test_batched_fixed_cycles_equal_single_mixed():
         s = mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
         um, _ = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
         assert rel_max(u.cpu().numpy(), um.cpu().numpy()) < 1e-4
+
+
+def test_single_problem_calls_reject_a_batched_handle():
+    """A batched handle has no levels of its own: every call of one problem
+    returns INVALID_ARG before it launches anything (and the handle still
+    solves afterwards)."""
+    mg = _gpu()
+    import ctypes as C
+    from paper_2505_05105_amd import _lib
+    L = _lib.lib()
+    probs = W.batched_draws(count=2, seed=1, sizes=(32, 64))
+    bs = mg.BatchedSolver([p.psi for p in probs], [p.N for p in probs])
+    n = (probs[0].N + 1) ** 2
+    a = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    b = torch.zeros_like(a)
+    hist = (C.c_double * 8)()
+    nc = C.c_int32(0)
+    J = C.c_double(0.0)
+    h, pa, pb = bs.handle, a.data_ptr(), b.data_ptr()
+    calls = {
+        "mgfem_solve": lambda: L.mgfem_solve(h, pa, pa, 1e-10, 5, 0, pb, hist, C.byref(nc)),
+        "mgfem_solve_mixed_bc": lambda: L.mgfem_solve_mixed_bc(h, pa, pa, None, 1e-10, 5, 0, pb, hist,
+                                                               C.byref(nc)),
+        "mgfem_adjoint": lambda: L.mgfem_adjoint(h, pa, 1e-10, 5, None, pb, None, hist, C.byref(nc)),
+        "mgfem_adjoint_neumann": lambda: L.mgfem_adjoint_neumann(h, pa, pb),
+        "mgfem_misfit": lambda: L.mgfem_misfit(h, pa, pa, C.byref(J), pb),
+        "mgfem_smooth": lambda: L.mgfem_smooth(h, 0, pa, pb, 1, 0),
+        "mgfem_export": lambda: L.mgfem_export(h, _lib.EXPORT_A, 0, pb),
+    }
+    for name, call in calls.items():
+        assert call() == _lib.ERR_INVALID_ARG, name
+    torch.cuda.synchronize()
+    us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
+    assert bs.last_status == 0
