@@ -231,7 +231,7 @@ int global_constant(const double* psi, const double* chi, int32_t N, const mgfem
                     double* C_out, int* iters_out);
 
 int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mgfem_params* pin, void* stream,
-               mgfem_handle* out, int op_kind = kOpAssembled) {
+               mgfem_handle* out, int op_kind = kOpAssembled, bool member = false) {
   if (!out) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!psi_dev) return fail(nullptr, MGFEM_ERR_INVALID_ARG, "psi_dev is NULL");
@@ -340,6 +340,10 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
   if (rc != MGFEM_OK) return bail(rc);
   rc = build_cut_rows(c);
   if (rc != MGFEM_OK) return bail(rc);
+  if (!member) {  // batch members run their coarse levels inside the batched kernel
+    rc = build_coarse_map(c);
+    if (rc != MGFEM_OK) return bail(rc);
+  }
   SETUP_TRY(hipStreamSynchronize(c->s));
   mgfem_info& I = c->info;
   I.N = N;
@@ -363,6 +367,12 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
 }
 
 }  // namespace
+
+namespace mgfem {
+int setup_member(const double* psi_dev, int32_t N, const mgfem_params* p, void* stream, mgfem_handle* out) {
+  return setup_impl(psi_dev, nullptr, N, p, stream, out, kOpAssembled, true);
+}
+}  // namespace mgfem
 
 extern "C" {
 

@@ -101,7 +101,7 @@ int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32
   };
   for (int i = 0; i < count; ++i) {
     mgfem_handle h = nullptr;
-    const int rc = mgfem_setup(psi_dev[i], N[i], &p, stream, &h);
+    const int rc = setup_member(psi_dev[i], N[i], &p, stream, &h);
     if (rc != MGFEM_OK) {
       const std::string why = mgfem_last_error(nullptr);
       return bail(rc, "problem " + std::to_string(i) + ": " + why);

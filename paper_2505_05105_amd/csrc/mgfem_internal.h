@@ -166,6 +166,19 @@ struct GraphEntry {
 // has not read yet survives the reductions of iterations queued after it.
 constexpr int kRedSlots = 8;
 
+// The coarse part of a cycle as a dense matrix (see k_coarse_apply): B maps
+// the right-hand side of the first coarse level's active nodes to the iterate
+// the coarse part leaves there, rows and columns in the order of idx.
+constexpr int kMaxMapNodes = 4096;  // larger first coarse levels keep the single-workgroup cycle
+struct CoarseMap {
+  int n = 0;             // active nodes of the first coarse level
+  int ld = 0;            // row stride (n rounded up to 16)
+  int reps = 0;          // cycles of the coarse part the map stands for
+  int* idx = nullptr;    // their grid indices on that level
+  double* f64[2] = {nullptr, nullptr};  // forward and transposed cycles, float64
+  float* f32 = nullptr;  // forward, float32 (the mixed-precision inner cycles)
+};
+
 // The coarsest levels run inside one workgroup, every array in LDS.
 constexpr int kDesc = 32;  // ints per coarse-level descriptor
 struct CoarsePlan {
@@ -184,6 +197,7 @@ struct CoarsePlan {
   int static64 = 0, static32 = 0;  // bytes of the static block (the image), whole 1 KB chunks
   int ndesc = 0;
   int lds64 = 0, lds32 = 0;
+  CoarseMap map;
 };
 
 struct Stats {
@@ -343,6 +357,12 @@ void run_cycle(mgfem_ctx* c, const CycleOpts& o);
 void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32);
 void gather_snap(mgfem_ctx* c, int l, bool fp32);
 int build_plans(mgfem_ctx* c);  // cut groups and the coarse single-workgroup layout
+// the coarse part as a dense map (forward and transposed, float64; float32
+// forward for mixed precision); skipped for batch members and large first
+// coarse levels, and when MGFEM_NO_COARSE_MAP=1 at set-up
+int build_coarse_map(mgfem_ctx* c);
+// mgfem_setup for one problem of a batched handle (no coarse map)
+int setup_member(const double* psi_dev, int32_t N, const mgfem_params* p, void* stream, mgfem_handle* out);
 int build_tile_lists(mgfem_ctx* c);
 // sweep tile shapes, all with 512 threads (a workgroup's load phase is bound
 // by the memory instructions each wave issues, so more waves per tile start

@@ -437,6 +437,17 @@ int build_plans(mgfem_ctx* c) {
   if ((rc = upload(c, &P.slot, slot))) return rc;
   if ((rc = upload(c, &P.cutl, cutl))) return rc;
   if ((rc = upload(c, &P.actl, actl))) return rc;
+  {
+    // grid indices of the first coarse level's active nodes in its list order
+    // (rows and columns of the coarse map)
+    const LevHost& h = hosts[0];
+    const int s0 = c->lv[lc].stride;
+    std::vector<int> gidx(std::max(1, h.nact));
+    for (int q = 0; q < h.nact; ++q)
+      gidx[q] = (h.ox + h.actl[q] % h.W) + (h.oy + h.actl[q] / h.W) * s0;
+    if ((rc = upload(c, &P.map.idx, gidx))) return rc;
+    P.map.n = h.nact;
+  }
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   set_kernel_attributes();
   return build_tile_lists(c);

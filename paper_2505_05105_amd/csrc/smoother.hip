@@ -695,6 +695,12 @@ struct CoarseArgs {
   int s_top;
   int nu1, nu2, eta, reverse, gstar;
   int reps;  // cycles of the first coarse level from its current iterate
+  // column mode (set-up of the coarse map): workgroup j runs the cycles on the
+  // unit right-hand side e_j (j-th node of the first coarse level's active
+  // list) and writes the result into column j of map_out (row stride map_ld)
+  int unit;
+  T* map_out;
+  int map_ld;
 };
 
 // pointers of one coarse level inside the LDS block
@@ -969,7 +975,10 @@ __device__ void coarse_body(const CoarseArgs<T>& a, unsigned char* base, int* sd
   }
   __syncthreads();
   // right-hand side of the first coarse level at its active nodes
-  {
+  if (a.unit) {
+    const WgLev<T> L = wg_level<T>(sdesc, base);
+    if (threadIdx.x == 0) L.b[L.act[blockIdx.x]] = T(1);
+  } else {
     const WgLev<T> L = wg_level<T>(sdesc, base);
     const int na = L.act_off[4];
     for (int t0 = 0; t0 < na; t0 += 8 * (int)blockDim.x) {
@@ -993,6 +1002,12 @@ __device__ void coarse_body(const CoarseArgs<T>& a, unsigned char* base, int* sd
   // reps cycles on the first coarse level, each continuing from the last
   for (int g = 0; g < a.reps; ++g) wg_cycle<T>(a, sdesc, base);
   const WgLev<T> L = wg_level<T>(sdesc, base);
+  if (a.unit) {
+    for (int t = threadIdx.x; t < L.act_off[4]; t += blockDim.x)
+      a.map_out[(int64_t)t * a.map_ld + blockIdx.x] = L.x[L.act[t]];
+    __syncthreads();
+    return;
+  }
   for (int t = threadIdx.x; t < L.act_off[4]; t += blockDim.x) {
     const int q = L.act[t];
     const int gi = L.ox + q % L.W, gj = L.oy + q / L.W;
@@ -1006,6 +1021,76 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse(CoarseArgs<T> a) {
   extern __shared__ __align__(16) unsigned char base[];
   __shared__ int sdesc[kDesc * kMaxWgLevels];
   coarse_body<T>(a, base, sdesc);
+}
+
+// The coarse part of a cycle as one dense product.  From a zero start the
+// cycles that k_coarse runs on the first coarse level (pre-smoothing,
+// restriction, the levels below, prolongation, post-smoothing, each a linear
+// step) map its right-hand side b to x = B b with a fixed matrix B, computed
+// at set-up by running those cycles on every unit vector.  Applying B reads
+// n^2 values with all CUs instead of running the ~250 barrier-separated
+// phases of the single-workgroup cycle.  One wave per row of B: the row is
+// loaded with 16-byte loads before b is gathered into LDS, then reduced
+// across the wave.
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+  using type = double2;
+  __device__ static double dot(const double2& v, const double* s) { return v.x * s[0] + v.y * s[1]; }
+};
+template <>
+struct Vec16<float> {
+  using type = float4;
+  __device__ static float dot(const float4& v, const float* s) {
+    return (v.x * s[0] + v.y * s[1]) + (v.z * s[2] + v.w * s[3]);
+  }
+};
+
+constexpr int kMapWaves = 4;  // rows of B per 256-thread workgroup
+
+template <class T>
+__global__ __launch_bounds__(64 * kMapWaves) void k_coarse_apply(const T* __restrict__ B, int ld,
+                                                                 const int* __restrict__ idx, int n,
+                                                                 const T* __restrict__ b, T* __restrict__ x) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* sb = reinterpret_cast<T*>(smem);
+  using V = typename Vec16<T>::type;
+  constexpr int G = 16 / (int)sizeof(T);  // values per 16-byte load
+  constexpr int U = 8;                    // loads in flight per lane
+  constexpr int CH = U * 64 * G;          // values of a row per round
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * kMapWaves + wave;
+  const T* row = B + (int64_t)(r < n ? r : 0) * ld;
+  V v[U];
+  auto load = [&](int base) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int col = base + (u * 64 + lane) * G;
+      v[u] = col < ld ? *reinterpret_cast<const V*>(row + col) : V{};
+    }
+  };
+  load(0);
+  for (int j = threadIdx.x; j < ld; j += blockDim.x) sb[j] = j < n ? b[idx[j]] : T(0);
+  __syncthreads();
+  T acc = T(0);
+  for (int base = 0;;) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int col = base + (u * 64 + lane) * G;
+      if (col < ld) acc += Vec16<T>::dot(v[u], sb + col);
+    }
+    base += CH;
+    if (base >= ld) break;
+    load(base);
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0 && r < n) x[idx[r]] = acc;
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q < n) d[q] = (float)s[q];
 }
 
 inline unsigned nblk(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); }
@@ -1201,8 +1286,9 @@ void prolong(mgfem_ctx* c, int l) {
                      Xp<T>(L, L.cur), L.flags, L.cutpos, Sp<T>(L), L.stride, L.bbox[0], L.bbox[2], ni, nj);
 }
 
+// arguments of k_coarse for `reps` cycles of the coarse part
 template <class T>
-void coarse_wg(mgfem_ctx* c, bool reverse, int reps) {
+CoarseArgs<T> coarse_args(mgfem_ctx* c, bool reverse, int reps) {
   CoarsePlan& P = c->cplan;
   Level& Lc = c->lv[P.lc];
   CoarseArgs<T> a;
@@ -1229,6 +1315,33 @@ void coarse_wg(mgfem_ctx* c, bool reverse, int reps) {
   a.reverse = reverse ? 1 : 0;
   a.gstar = c->p.cycle == MGFEM_CYCLE_W ? 2 : 1;
   a.reps = reps;
+  a.unit = 0;
+  a.map_out = nullptr;
+  a.map_ld = 0;
+  return a;
+}
+
+template <class T>
+const T* coarse_map(const CoarseMap& M, bool reverse);
+template <>
+const double* coarse_map<double>(const CoarseMap& M, bool reverse) { return M.f64[reverse ? 1 : 0]; }
+template <>
+const float* coarse_map<float>(const CoarseMap& M, bool reverse) { return reverse ? nullptr : M.f32; }
+
+template <class T>
+void coarse_wg(mgfem_ctx* c, bool reverse, int reps) {
+  CoarsePlan& P = c->cplan;
+  Level& Lc = c->lv[P.lc];
+  const T* B = coarse_map<T>(P.map, reverse);
+  if (B && reps == P.map.reps) {
+    const int n = P.map.n;
+    hipLaunchKernelGGL(k_coarse_apply<T>, dim3(nblk(n, kMapWaves)), dim3(64 * kMapWaves),
+                       P.map.ld * sizeof(T), c->s, B, P.map.ld, (const int*)P.map.idx, n,
+                       (const T*)Bp<T>(Lc), Xp<T>(Lc, 0));
+    Lc.cur = 0;
+    return;
+  }
+  const CoarseArgs<T> a = coarse_args<T>(c, reverse, reps);
   const int lds = std::is_same<T, double>::value ? P.lds64 : P.lds32;
   hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kCoarseThreads), lds, c->s, a);
   Lc.cur = 0;
@@ -1436,6 +1549,40 @@ int build_tile_lists(mgfem_ctx* c) {
       MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
       L.rr_ntiles = (int)rl.size();
     }
+  }
+  MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  return MGFEM_OK;
+}
+
+int build_coarse_map(mgfem_ctx* c) {
+  CoarsePlan& P = c->cplan;
+  CoarseMap& M = P.map;
+  if (P.lc < 0 || M.n <= 0 || M.n > kMaxMapNodes) return MGFEM_OK;
+  {
+    const char* env = std::getenv("MGFEM_NO_COARSE_MAP");
+    if (env && env[0] && env[0] != '0') return MGFEM_OK;
+  }
+  // the cycles one coarse-part launch runs: gamma* (the two-grid scheme solves
+  // its first coarse problem with coarse_cycles cycles when that problem is
+  // the first level of the coarse part)
+  const bool two_grid = c->p.cycle == MGFEM_CYCLE_TWO_GRID && P.lc == 1;
+  M.reps = two_grid ? c->p.coarse_cycles : (c->p.cycle == MGFEM_CYCLE_W ? 2 : 1);
+  M.ld = (M.n + 15) / 16 * 16;
+  const size_t cnt = (size_t)M.ld * M.n;
+  for (int rev = 0; rev < 2; ++rev) {
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &M.f64[rev], cnt));  // zeroed: the padding columns stay 0
+    CoarseArgs<double> a = coarse_args<double>(c, rev != 0, M.reps);
+    a.unit = 1;
+    a.map_out = M.f64[rev];
+    a.map_ld = M.ld;
+    hipLaunchKernelGGL(k_coarse<double>, dim3(M.n), dim3(kCoarseThreads), P.lds64, c->s, a);
+    MGFEM_HIP_TRY(hipGetLastError());
+  }
+  if (c->p.precision == MGFEM_PREC_MIXED) {
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &M.f32, cnt));
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(nblk((int64_t)cnt, 256)), dim3(256), 0, c->s,
+                       (const double*)M.f64[0], M.f32, (int64_t)cnt);
+    MGFEM_HIP_TRY(hipGetLastError());
   }
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
   return MGFEM_OK;

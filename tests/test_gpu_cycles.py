@@ -59,6 +59,32 @@ def test_two_grid_iterates_match_oracle(reverse):
         assert rel_max(lam.cpu().numpy(), ref.u) < 1e-10
 
 
+@pytest.mark.parametrize("N", [512, 1024])
+@pytest.mark.parametrize("reverse", [False, True], ids=["forward", "transposed"])
+def test_w_cycle_iterates_on_several_tiled_levels(N, reverse):
+    """W-cycles (gamma* = 2) where several levels above the coarse part run
+    the tiled kernels and are visited 2, 4, 8 times per cycle: iterates after
+    3 cycles against the oracle's recursion, to the float64 solution bar of
+    1e-10 relative (the coarse part, 2 W-cycles of the levels below, is
+    applied as its dense map, whose products round differently from the
+    oracle's recursion: measured 8e-12)."""
+    mg = _gpu()
+    p = W.flower_mms(N)
+    d = oasm.assemble(p.psi, N)
+    H = omg.build_hierarchy(d)
+    s = mg.Solver(p.psi, N, cycle=mg.CYCLE_W)
+    if not reverse:
+        u, hist = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
+        ref = omg.solve(H, d.rhs(p.f, p.g), tol=-1.0, max_cycles=3, gamma_star=2)
+        assert rel_max(u.cpu().numpy(), ref.u) < 1e-10
+        np.testing.assert_allclose(hist, ref.hist, rtol=1e-8, atol=50 * 2.2e-16 * hist[0])
+    else:
+        r = np.random.default_rng(5).standard_normal(d.n) * d.active
+        _, _, lam, hist = s.adjoint(r, tol=-1.0, max_cycles=3)
+        ref = omg.solve(H, r, tol=-1.0, max_cycles=3, nu1=1, nu2=2, gamma_star=2, reverse=True)
+        assert rel_max(lam.cpu().numpy(), ref.u) < 1e-10
+
+
 def test_two_grid_converges_like_the_oracle():
     mg = _gpu()
     N = 256

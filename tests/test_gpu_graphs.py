@@ -178,3 +178,41 @@ def test_profiled_mixed_replay_times_the_float_sweep():
     assert np.array_equal(h0, h1) and torch.equal(u0, u1)
     assert prof["launches"] == 3 * (len(h1) - 1)
     assert prof["total_ms"] > 0 and prof["alg_bytes"] > 0
+
+
+def _solver_env(mg, p, N, env, **kw):
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return mg.Solver(p.psi, N, chi=p.chi, **kw)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("kw", [{}, {"cycle": 2}, {"cycle": 3}, {"precision": 1}],
+                         ids=["V", "W", "two_grid", "mixed"])
+def test_coarse_map_equals_the_coarse_cycle(kw):
+    """The coarse part applied as its precomputed dense map (the default)
+    against the single-workgroup cycle it stands for (MGFEM_NO_COARSE_MAP=1):
+    the same linear map, so iterates agree up to rounding, forward and
+    transposed."""
+    mg = _gpu()
+    N = 256
+    p = W.flower_mms(N)
+    sm = _solver_env(mg, p, N, {"MGFEM_NO_COARSE_MAP": "0"}, **kw)
+    sc = _solver_env(mg, p, N, {"MGFEM_NO_COARSE_MAP": "1"}, **kw)
+    tol = 1e-5 if kw.get("precision") == 1 else 1e-12
+    um, hm = sm.solve(p.f, p.g, tol=-1.0, max_cycles=4)
+    uc, hc = sc.solve(p.f, p.g, tol=-1.0, max_cycles=4)
+    scale = float(uc.abs().max())
+    assert float((um - uc).abs().max()) <= tol * scale
+    np.testing.assert_allclose(hm, hc, rtol=max(tol, 1e-9) * 100, atol=50 * 2.2e-16 * hc[0])
+    if kw.get("precision") != 1:
+        r = torch.tensor(np.random.default_rng(2).standard_normal(um.numel()), device=um.device)
+        _, _, lm, _ = sm.adjoint(r, tol=-1.0, max_cycles=3)
+        _, _, lc, _ = sc.adjoint(r, tol=-1.0, max_cycles=3)
+        assert float((lm - lc).abs().max()) <= 1e-12 * float(lc.abs().max())
