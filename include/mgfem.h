@@ -232,6 +232,22 @@ int mgfem_adjoint_neumann(mgfem_handle h, const double* lam_dev, double* dJdgN_d
 int mgfem_misfit(mgfem_handle h, const double* u_dev, const double* ut_dev, double* J_host,
                  double* dJdu_dev);
 
+/*
+ * mgfem_misfit for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops): same arguments, results and
+ * errors, computed by one fused pass whose only scratch (one partial sum per
+ * 256 x 4 block of the grid) lives in a static 2 MiB device array of the
+ * library instead of memory it allocates.  The call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine.
+ *  Limit: (N/256 + 1)(N/4 + 1) partial sums of 8 bytes must fit in 2 MiB
+ *         (every N below 16384); a larger N returns INVALID_ARG with the sizes.
+ *  Every call on one device shares that array and leaves its partials in
+ *  it: calls that overlap on one device (other streams, other host
+ *  threads) race.  Synchronises the handle's stream.
+ */
+int mgfem_misfit_noalloc(mgfem_handle h, const double* u_dev, const double* ut_dev, double* J_host,
+                         double* dJdu_dev);
+
 /* Counts and extrema of the setup (fills *info). */
 int mgfem_query(mgfem_handle h, mgfem_info* info);
 
@@ -293,9 +309,15 @@ int mgfem_level_counts(mgfem_handle h, int32_t level, int64_t* n_active, int64_t
  * algorithmic bytes of those launches are accumulated.  Class 0 is the
  * float64 full-sweep kernel of the finest level, class 1 the float32 one of
  * the mixed-precision cycles; the algorithmic bytes per launch are, with w
- * the value size (8 or 4), 3w + 1 per active row (iterate read and written,
- * right-hand side, flag byte) plus 9w per stored row, plus w per active
- * coarse row when the sweep applies the prolongation.
+ * the value size (8 or 4), 3w per active row (iterate read and written,
+ * right-hand side) plus 9w per stored row, plus w per active coarse row when
+ * the sweep applies the prolongation (the one flag byte per node it also
+ * reads is not counted).
+ *  enable : 0 off, 1 on, R in 2..1000: each timed launch is issued R times
+ *           back to back between its two events (the sweep reads one iterate
+ *           buffer and writes the other, so a repeat recomputes the same
+ *           values) and its time is the elapsed time / R, which leaves out
+ *           the dispatch gap an event pair adds to a single launch.
  * mgfem_profile resets the counters.
  */
 int mgfem_profile(mgfem_handle h, int32_t enable);

@@ -28,6 +28,7 @@ EXPORTED = (
     "mgfem_status_string", "mgfem_last_error", "mgfem_setup_batched", "mgfem_solve_batched",
     "mgfem_level_counts", "mgfem_profile", "mgfem_profile_read", "mgfem_batched_tile",
     "mgfem_setup_mixed_bc", "mgfem_solve_mixed_bc", "mgfem_adjoint_neumann", "mgfem_residual_l2",
+    "mgfem_misfit_noalloc",
 )
 
 
@@ -73,6 +74,7 @@ def lib():
         "mgfem_adjoint_neumann": (C.c_int, [P, P, P]),
         "mgfem_adjoint": (C.c_int, [P, P, D, I32, P, P, P, DP, C.POINTER(I32)]),
         "mgfem_misfit": (C.c_int, [P, P, P, DP, P]),
+        "mgfem_misfit_noalloc": (C.c_int, [P, P, P, DP, P]),
         "mgfem_query": (C.c_int, [P, C.POINTER(Info)]),
         "mgfem_export": (C.c_int, [P, I32, I32, P]),
         "mgfem_level_n": (I32, [P, I32]),

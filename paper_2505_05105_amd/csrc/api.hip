@@ -303,8 +303,13 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
     const int64_t tiles = (int64_t)(N / 16 + 2) * (N / 16 + 2);
     SETUP_TRY(ctx_alloc_t(c, &c->sweep_part, 2 * tiles));
   }
-  SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 4 * kRedSlots * sizeof(double)));
-  for (int q = 0; q < 4 * kRedSlots; ++q) c->red_host[q] = 0.0;
+  // the ring of norm records, and one more record for mgfem_misfit_noalloc
+  SETUP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->red_host), 4 * (kRedSlots + 1) * sizeof(double)));
+  for (int q = 0; q < 4 * (kRedSlots + 1); ++q) c->red_host[q] = 0.0;
+  if (scratch_init(&c->device) != MGFEM_OK) {
+    c->last_error = "hipGetDevice failed";
+    return bail(MGFEM_ERR_HIP);
+  }
   {
     const char* env = std::getenv("MGFEM_NO_GRAPHS");
     c->use_graphs = !(env && env[0] && env[0] != '0');

@@ -280,6 +280,7 @@ struct mgfem_ctx {
   double f_l2 = 0.0;                // ||F||_2 of the right-hand side the last solve assembled
   std::vector<double> l2_hist;      // ||F - A u_m||_2 of the last solve or adjoint, m = 0..cycles
   std::string last_error;
+  int device = 0;                   // device that was current at set-up
   bool batched_member = false;
   std::vector<mgfem_ctx*> members;  // batched handle: one context per problem
   mgfem::BatchDevice batch;
@@ -361,6 +362,9 @@ int build_plans(mgfem_ctx* c);  // cut groups and the coarse single-workgroup la
 // forward for mixed precision); skipped for batch members and large first
 // coarse levels, and when MGFEM_NO_COARSE_MAP=1 at set-up
 int build_coarse_map(mgfem_ctx* c);
+// the device-side address of the static scratch array of the current device,
+// looked up once per device (noalloc.hip); *device receives that device
+int scratch_init(int* device);
 // mgfem_setup for one problem of a batched handle (no coarse map)
 int setup_member(const double* psi_dev, int32_t N, const mgfem_params* p, void* stream, mgfem_handle* out);
 int build_tile_lists(mgfem_ctx* c);
