@@ -54,9 +54,10 @@ def measured_traffic(domain="flower", N=4096):
         return None
     if t.get("source_hash") != source_hash():
         return None
-    if t.get("workload") != {"domain": domain, "N": N}:
-        return None
-    return t.get("bytes_per_launch")
+    for rec in t.get("records", []):
+        if rec.get("workload") == {"domain": domain, "N": N}:
+            return rec.get("bytes_per_launch")
+    return None
 
 
 def parse():
@@ -68,7 +69,11 @@ def parse():
     ap.add_argument("--domain", default="flower", choices=["flower", "ellipse"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=3)
+    ap.add_argument("--cpu-solves", type=int, default=3, help="oracle solves timed (median reported)")
+    ap.add_argument("--profile-repeat", type=int, default=10,
+                    help="each timed sweep launch repeated back to back between its events")
+    ap.add_argument("--no-hbm", action="store_true", help="skip the N=16384 leg (working set above the MALL)")
+    ap.add_argument("--hbm-N", type=int, default=16384)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint and further-form legs")
     ap.add_argument("--batch", type=int, default=256)
@@ -81,11 +86,11 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(prob, N, gpu_cycles, cycles):
-    """The oracle, as it stands, on a bounded sample of the same workload:
-    its setup, then `cycles` V-cycles at full size; the per-cycle time is
-    scaled to the cycle count the solve needs (the oracle runs the same
-    cycles, so it needs the same count)."""
+def cpu_baseline(prob, N, solves):
+    """The oracle, as it stands, on the same workload: its set-up (timed
+    apart), then `solves` full solves to the same tolerance from zero; the
+    median solve time gives DOF/s.  One thread (scipy's sparse products are
+    single-threaded; BLAS pools are limited to one thread by the caller)."""
     import numpy as np
     from oracle import assembly as oasm
     from oracle import multigrid as omg
@@ -93,19 +98,20 @@ def cpu_baseline(prob, N, gpu_cycles, cycles):
     d = oasm.assemble(prob.psi, N)
     H = omg.build_hierarchy(d)
     t1 = time.perf_counter()
-    F = d.rhs(prob.f, prob.g)
-    t2 = time.perf_counter()
-    res = omg.solve(H, F, tol=-1.0, max_cycles=cycles)
-    t3 = time.perf_counter()
-    per_cycle = (t3 - t2) / cycles
+    times, res = [], None
+    for _ in range(solves):
+        ts = time.perf_counter()
+        F = d.rhs(prob.f, prob.g)
+        res = omg.solve(H, F, tol=1e-10, max_cycles=60)
+        times.append(time.perf_counter() - ts)
+    med = float(np.median(times))
     dof = int(d.active.sum())
-    solve_s = per_cycle * gpu_cycles
     return {
-        "value": dof / solve_s, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-        "sample": f"numpy/scipy oracle at N={N}: setup ({t1 - t0:.1f} s) then {cycles} V(2,1) "
-                  f"cycles ({t3 - t2:.1f} s), per-cycle time x {gpu_cycles} cycles to 1e-10",
-        "setup_s": t1 - t0, "per_cycle_s": per_cycle,
-        "hist": [float(x) for x in res.hist],
+        "value": dof / med, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+        "sample": f"numpy/scipy oracle at N={N}: set-up ({t1 - t0:.1f} s, not in the value), then {solves} "
+                  f"full solves to 1e-10 ({res.cycles} cycles each), median {med:.2f} s",
+        "setup_s": t1 - t0, "solve_s": times, "cycles": int(res.cycles),
+        "hist": [float(x) for x in res.hist], "u": res.u,
         "cpu": _cpu_name(), "nproc": os.cpu_count(),
     }
 
@@ -278,6 +284,138 @@ def bench_next(args, mg, W, torch, dev, N=4096, oracle_N=1024, with_oracle=True)
     return out
 
 
+def sweep_roofline(solver, solve, kernel_class, steps, repeat, traffic):
+    """Roofline of the finest-level sweep (class 0 float64, class 1 the float32
+    sweep of the mixed cycles), measured live: the solves again with HIP events
+    on the solver's stream around every launch of that kernel, each launch
+    issued `repeat` times back to back between its two events (the sweep
+    reads one iterate buffer and writes the other, so a repeat recomputes the
+    same values) so that the event pair's dispatch gap is spread over the
+    repeats.  Algorithmic bytes per launch (matrix-free count): 3 values per
+    active row (iterate read and written, right-hand side), 9 per stored row,
+    1 per active coarse row when the prolongation is fused; the one flag byte
+    per node the kernel also reads is reported apart."""
+    solver.profile(True, repeat=repeat)
+    solve()  # captures the profiled graphs
+    torch_sync()
+    solver.profile(True, repeat=repeat)  # reset the counters
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solve()
+    torch_sync()
+    prof_ms = (time.perf_counter() - t0) * 1e3 / steps
+    prof = solver.profile_read(kernel_class)
+    solver.profile(False)
+    launches = max(prof["launches"], 1)
+    avg_ms = prof["total_ms"] / launches
+    alg = prof["alg_bytes"] / launches
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    vb = 8 if kernel_class == 0 else 4
+    kernel = SWEEP_KERNEL if kernel_class == 0 else SWEEP_KERNEL.replace("double", "float")
+    log(f"[bench] {kernel}: {prof['launches']} launches, avg {avg_ms * 1e3:.2f} us "
+        f"(x{repeat} back to back), {alg / 1e6:.1f} MB algorithmic -> {achieved:.0f} GB/s")
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": alg,
+            "flag_bytes_per_launch": solver.level_counts(0)["n_active"],
+            "byte_model": f"{3 * vb} B per active row + {9 * vb} B per stored row + {vb} B per active "
+                          f"coarse row when the prolongation is fused (matrix-free interior rows)",
+            "launches": prof["launches"], "repeat_per_event_pair": repeat,
+            "profiled_ms_per_step": prof_ms}
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def bench_hbm(args, mg, W, torch, dev):
+    """The same float64 solve on the flower at N = args.hbm_N (16384: 53.8M
+    active DOF, 268M grid nodes): its level-0 vectors (about 0.5 GB each over
+    the active box) are far larger than the 256 MB last-level cache, so the
+    finest sweep's bytes come from HBM.  Inputs are generated on the device
+    with the flower workload's formulas."""
+    N = args.hbm_N
+    log(f"[bench] hbm leg: setup N={N} flower")
+    psi, f, g = W.flower_mms_device(N, dev)
+    t0 = time.perf_counter()
+    s = mg.Solver(psi, N)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    del psi
+    u = torch.empty((N + 1) ** 2, dtype=torch.float64, device=dev)
+
+    def run():
+        return s.solve(f, g, tol=args.tol, max_cycles=100, out=u)[1]
+
+    hist = run()
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        hist = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    dof = s.info()["n_active"]
+    log(f"[bench] hbm leg N={N}: {ms:.2f} ms/solve, {len(hist) - 1} cycles, {dof / (ms * 1e-3) / 1e9:.3f} GDOF/s")
+    roof = sweep_roofline(s, run, 0, steps, args.profile_repeat, measured_traffic("flower", N))
+    roof.update({"workload": f"flower ghost-FEM Poisson, N={N}, V(2,1), eta=4, gamma=2, rel_tol={args.tol:g}",
+                 "N": N, "active_dof": dof, "cycles": len(hist) - 1, "ms_per_solve": ms,
+                 "dof_per_s": dof / (ms * 1e-3), "setup_s": setup_s,
+                 "final_rel_residual": float(hist[-1] / hist[0])})
+    s.close()
+    del f, g, u
+    torch.cuda.empty_cache()
+    return roof
+
+
+def bench_ellipse_mixed(args, mg, W, torch, dev, with_oracle):
+    """The ellipse (0.7, 0.35) rotated 0.3 at N = 4096: float64 and mixed
+    solves to the same tolerance, the mixed solution's error against the
+    float64 GPU solution and, with the oracle, against the oracle's float64
+    solution (one set-up and one solve on a host core)."""
+    N = 4096
+    prob = W.ellipse_mms(N)
+    f = torch.tensor(prob.f, device=dev)
+    g = torch.tensor(prob.g, device=dev)
+    psi = torch.tensor(prob.psi, device=dev)
+    rec = {}
+    sols = {}
+    for name, prec in (("fp64", mg.PREC_FP64), ("mixed", mg.PREC_MIXED)):
+        s = mg.Solver(psi, N, precision=prec)
+        u = torch.empty((N + 1) ** 2, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup):
+            _, h = s.solve(f, g, tol=args.tol, max_cycles=100, out=u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, h = s.solve(f, g, tol=args.tol, max_cycles=100, out=u)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        dof = s.info()["n_active"]
+        rec[name] = {"ms_per_step": ms, "value": dof / (ms * 1e-3), "unit": "DOF/s", "cycles": len(h) - 1,
+                     "final_rel_residual": float(h[-1] / h[0])}
+        sols[name] = u
+        s.close()
+        log(f"[bench] ellipse {name}: {ms:.3f} ms/solve, {len(h) - 1} cycles")
+    rec["active_dof"] = dof
+    rec["mixed"]["speedup_vs_fp64"] = rec["fp64"]["ms_per_step"] / rec["mixed"]["ms_per_step"]
+    u64, umx = sols["fp64"], sols["mixed"]
+    rec["mixed"]["rel_err_vs_fp64_gpu"] = float((umx - u64).abs().max() / u64.abs().max())
+    if with_oracle:
+        from oracle import assembly as oasm
+        from oracle import multigrid as omg
+        d = oasm.assemble(prob.psi, N)
+        ref = omg.solve(omg.build_hierarchy(d), d.rhs(prob.f, prob.g), tol=args.tol, max_cycles=60)
+        uo = torch.tensor(ref.u, device=dev)
+        scale = uo.abs().max()
+        rec["mixed"]["rel_err_vs_fp64_oracle"] = float((umx - uo).abs().max() / scale)
+        rec["fp64"]["rel_err_vs_fp64_oracle"] = float((u64 - uo).abs().max() / scale)
+        rec["oracle_cycles"] = int(ref.cycles)
+        log(f"[bench] ellipse: mixed error vs the float64 oracle {rec['mixed']['rel_err_vs_fp64_oracle']:.2e}")
+    return rec
+
+
 def _final_l2(solver):
     """||F - A u||_2 / ||F||_2 after the solver's last solve (it recorded it)."""
     l2 = solver.residual_l2()
@@ -347,27 +485,8 @@ def main():
     ms = (t1 - t0) * 1e3 / args.steps
     cycles = len(hist) - 1
     log(f"[bench] fp64: {ms:.3f} ms/solve, {cycles} cycles, {dof / (ms * 1e-3) / 1e9:.3f} GDOF/s")
-    # the same steps again with HIP events around every launch of the sweep
-    # kernel (the timed launch runs between graph segments on the solver's
-    # stream); one untimed profiled solve first captures those graphs
-    s64.profile(True)
-    run(s64, u)
-    torch.cuda.synchronize()
-    s64.profile(True)  # reset the counters
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        hist = run(s64, u)
-    torch.cuda.synchronize()
-    prof_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    prof = s64.profile_read(0)
-    s64.profile(False)
-    avg_ms = prof["total_ms"] / max(prof["launches"], 1)
-    alg = prof["alg_bytes"] / max(prof["launches"], 1)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.domain, N)
-    log(f"[bench] {SWEEP_KERNEL}: {prof['launches']} launches, avg {avg_ms * 1e3:.2f} us, "
-        f"{alg / 1e6:.1f} MB algorithmic -> {achieved:.0f} GB/s")
-
+    roof = sweep_roofline(s64, lambda: run(s64, u), 0, args.steps, args.profile_repeat,
+                          measured_traffic(args.domain, N))
     out = {
         "metric": METRIC, "value": dof / (ms * 1e-3), "unit": "DOF/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
@@ -380,13 +499,11 @@ def main():
         "setup_ms": info["setup_ms"],
         "final_rel_residual": float(hist[-1] / hist[0]),
         "final_rel_residual_l2": _final_l2(s64),
-        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "avg_launch_us": avg_ms * 1e3, "alg_bytes_per_launch": alg,
-                     "launches": prof["launches"], "profiled_ms_per_step": prof_ms},
+        "roofline": roof,
         "levels": [dict(N=s64.level_n(l), **s64.level_counts(l)) for l in range(info["n_levels"])],
     }
 
+    u_mixed = None
     if not args.no_mixed:
         smx = mg.Solver(psi, N, precision=mg.PREC_MIXED)
         um = torch.empty_like(u)
@@ -400,33 +517,26 @@ def main():
         t1 = time.perf_counter()
         msm = (t1 - t0) * 1e3 / args.steps
         err = float((um - u).abs().max() / u.abs().max())
-        # the float32 finest sweep timed the same way (events around each launch)
-        smx.profile(True)
-        run(smx, um)
-        torch.cuda.synchronize()
-        smx.profile(True)
-        for _ in range(args.steps):
-            run(smx, um)
-        torch.cuda.synchronize()
-        pm = smx.profile_read(1)
-        smx.profile(False)
-        avg32 = pm["total_ms"] / max(pm["launches"], 1)
-        alg32 = pm["alg_bytes"] / max(pm["launches"], 1)
-        ach32 = alg32 / (avg32 * 1e-3) / 1e9 if pm["launches"] else 0.0
+        u_mixed = um.cpu().numpy()
+        # the float32 finest sweep timed the same way
+        roof32 = sweep_roofline(smx, lambda: run(smx, um), 1, args.steps, args.profile_repeat, None)
         out["mixed"] = {"value": dof / (msm * 1e-3), "unit": "DOF/s", "ms_per_step": msm,
                         "cycles": len(hm) - 1, "dtype": "f32 cycles / f64 outer",
-                        "rel_err_vs_fp64": err, "final_rel_residual": float(hm[-1] / hm[0]),
-                        "speedup_vs_fp64": ms / msm,
-                        "roofline": {"bound": "hbm", "kernel": SWEEP_KERNEL.replace("double", "float"),
-                                     "achieved": ach32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": ach32 / HBM_PEAK_GBS, "traffic": None,
-                                     "avg_launch_us": avg32 * 1e3, "alg_bytes_per_launch": alg32,
-                                     "launches": pm["launches"]}}
+                        "rel_err_vs_fp64_gpu": err, "final_rel_residual": float(hm[-1] / hm[0]),
+                        "speedup_vs_fp64": ms / msm, "roofline": roof32}
         log(f"[bench] mixed: {msm:.3f} ms/solve, {len(hm) - 1} cycles, err vs fp64 {err:.2e}")
         smx.close()
 
+    u_fp64 = u.cpu().numpy()
+    s64.close()
+    if not args.no_hbm:
+        del f, g, psi, u
+        torch.cuda.empty_cache()
+        out["roofline_hbm"] = bench_hbm(args, mg, W, torch, dev)
+
     if not args.no_extras:
-        s64.close()
+        with _one_thread():
+            out["ellipse"] = bench_ellipse_mixed(args, mg, W, torch, dev, not args.no_cpu_baseline)
         out["batched"] = bench_batched(args, mg, W, torch, dev)
         out["adjoint"] = bench_adjoint(args, mg, W, torch, dev)
         with _one_thread():
@@ -446,11 +556,16 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         with _one_thread():
-            out["cpu_baseline"] = cpu_baseline(prob, N, cycles, args.cpu_cycles)
+            out["cpu_baseline"] = cpu_baseline(prob, N, args.cpu_solves)
+        uo = out["cpu_baseline"].pop("u")
+        if "mixed" in out and u_mixed is not None:
+            out["mixed"]["rel_err_vs_fp64_oracle"] = float(np.abs(u_mixed - uo).max() / np.abs(uo).max())
+        out["fp64_rel_err_vs_oracle"] = float(np.abs(u_fp64 - uo).max() / np.abs(uo).max())
         hc = np.array(out["cpu_baseline"].pop("hist"))
-        k = len(hc)
+        out["cpu_baseline"]["same_cycle_count_as_gpu"] = len(hc) == len(hist)
+        k = min(len(hc), len(hist))
         out["cpu_baseline"]["hist_rel_diff_vs_gpu"] = float(
-            np.max(np.abs(hc - hist[:k]) / np.abs(hist[:k])))
+            np.max(np.abs(hc[:k] - hist[:k]) / np.abs(hist[:k])))
     print(json.dumps(out), flush=True)
 
 

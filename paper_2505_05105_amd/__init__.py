@@ -182,9 +182,10 @@ class Solver:
                    self.handle)
         return {"n_active": a.value, "n_stored": s.value, "n_cut": c.value}
 
-    def profile(self, enable=True):
-        """Enable HIP-event timing of the profiled kernel class (resets the counters)."""
-        _lib.check(_lib.lib().mgfem_profile(self.handle, 1 if enable else 0), self.handle)
+    def profile(self, enable=True, repeat=1):
+        """Enable HIP-event timing of the profiled kernel class (resets the
+        counters); repeat > 1 times each profiled launch repeated back to back."""
+        _lib.check(_lib.lib().mgfem_profile(self.handle, (max(1, int(repeat)) if enable else 0)), self.handle)
 
     def profile_read(self, kernel_class=0):
         n, ms, b = C.c_int64(), C.c_double(), C.c_double()

@@ -123,7 +123,7 @@ void prof_launch(mgfem_ctx* c, int kernel_class, double bytes, std::function<voi
     P.ev.push_back(e);
   }
   (void)hipEventRecord(P.ev[2 * slot], c->s);
-  launch(c->s);
+  for (int r = 0; r < P.repeat; ++r) launch(c->s);
   (void)hipEventRecord(P.ev[2 * slot + 1], c->s);
   P.pending.push_back({kernel_class, bytes});
 }
@@ -136,7 +136,7 @@ void prof_collect(mgfem_ctx* c) {
     if (hipEventElapsedTime(&ms, P.ev[2 * i], P.ev[2 * i + 1]) != hipSuccess) continue;
     const int k = P.pending[i].first;
     P.launches[k] += 1;
-    P.ms[k] += ms;
+    P.ms[k] += ms / P.repeat;
     P.bytes[k] += P.pending[i].second;
   }
   P.pending.clear();
@@ -150,7 +150,7 @@ static int prof_collect_graph(mgfem_ctx* c, const GraphEntry& g) {
     float ms = 0.f;
     MGFEM_HIP_TRY(hipEventElapsedTime(&ms, sl.beg, sl.end));
     P.launches[sl.kernel_class] += 1;
-    P.ms[sl.kernel_class] += ms;
+    P.ms[sl.kernel_class] += ms / P.repeat;
     P.bytes[sl.kernel_class] += sl.bytes;
   }
   return MGFEM_OK;
@@ -565,7 +565,7 @@ int run_iteration(mgfem_ctx* c, const IterKind& k, const GraphEntry** used) {
   for (const GraphSeg& sg : g.segs) {
     if (sg.launch) {
       MGFEM_HIP_TRY(hipEventRecord(g.slots[sg.slot].beg, c->s));
-      sg.launch(c->s);
+      for (int r = 0; r < c->prof.repeat; ++r) sg.launch(c->s);
       MGFEM_HIP_TRY(hipEventRecord(g.slots[sg.slot].end, c->s));
     } else {
       MGFEM_HIP_TRY(hipGraphLaunch(sg.exec, c->s));
@@ -985,8 +985,9 @@ int mgfem_level_counts(mgfem_handle c, int32_t level, int64_t* n_active, int64_t
 }
 
 int mgfem_profile(mgfem_handle c, int32_t enable) {
-  if (!c) return MGFEM_ERR_INVALID_ARG;
+  if (!c || enable < 0 || enable > 1000) return MGFEM_ERR_INVALID_ARG;
   c->prof.on = enable != 0;
+  c->prof.repeat = enable > 1 ? enable : 1;
   for (int k = 0; k < 4; ++k) {
     c->prof.launches[k] = 0;
     c->prof.ms[k] = 0.0;

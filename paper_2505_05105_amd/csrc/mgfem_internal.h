@@ -127,6 +127,7 @@ struct Level {
 // HIP-event timing of one kernel class inside a solve (see mgfem_profile)
 struct Profiler {
   bool on = false;
+  int repeat = 1;              // back-to-back launches between one event pair (time / repeat)
   std::vector<hipEvent_t> ev;  // pairs
   std::vector<std::pair<int, double>> pending;  // (kernel class, algorithmic bytes)
   std::vector<hipEvent_t> cap_ev;  // pairs used by graph segments (created outside any capture)

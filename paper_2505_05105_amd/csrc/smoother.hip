@@ -478,31 +478,45 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
 #pragma unroll
     for (int e = 0; e < 8; ++e) rcf[c][e] = scoef[8 * tt + e];
   }
-  for (int sweep = 0; sweep < a.eta; ++sweep) {
+  // one colour phase; called with a literal colour so that the register
+  // arrays above are indexed by constants (a run-time index would move them
+  // to scratch memory)
+  auto phase = [&](const int c) {
+    if (rt[c] >= 0) {
+      T nb[8];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int c = a.reverse ? 3 - p : p;
-      if (rt[c] >= 0) {
-        T nb[8];
+      for (int e = 0; e < 8; ++e) nb[e] = vals[rrf[c].r[e]];
+      T acc = rb[c];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) nb[e] = vals[rrf[c].r[e]];
-        T acc = rb[c];
+      for (int e = 0; e < 8; ++e) acc -= rcf[c][e] * nb[e];
+      vals[rt[c]] = acc * rinv[c];
+    }
+    const int lo = gi[4 + c] + blockDim.x, hi = gi[5 + c];
+    for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+      const Refs8 rr = srefs[t];
+      T nb[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc -= rcf[c][e] * nb[e];
-        vals[rt[c]] = acc * rinv[c];
-      }
-      const int lo = gi[4 + c] + blockDim.x, hi = gi[5 + c];
-      for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-        const Refs8 rr = srefs[t];
-        T nb[8];
+      for (int e = 0; e < 8; ++e) nb[e] = vals[rr.r[e]];
+      T acc = sb[t];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) nb[e] = vals[rr.r[e]];
-        T acc = sb[t];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) acc -= scoef[8 * t + e] * nb[e];
-        vals[t] = acc * sinv[t];
-      }
-      __syncthreads();
+      for (int e = 0; e < 8; ++e) acc -= scoef[8 * t + e] * nb[e];
+      vals[t] = acc * sinv[t];
+    }
+    __syncthreads();
+  };
+  if (!a.reverse) {
+    for (int sweep = 0; sweep < a.eta; ++sweep) {
+      phase(0);
+      phase(1);
+      phase(2);
+      phase(3);
+    }
+  } else {
+    for (int sweep = 0; sweep < a.eta; ++sweep) {
+      phase(3);
+      phase(2);
+      phase(1);
+      phase(0);
     }
   }
 #pragma unroll
@@ -1166,11 +1180,14 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   a.tc_pos = L.tc_pos;
   a.zero = reinterpret_cast<const T*>(c->zero);
   if (c->prof.on && l == 0) {
-    // algorithmic bytes: per active row x read and written, b read, its flag,
-    // the nine coefficients of a stored row; a fused prolongation also reads
-    // x_c (class 0 float64, class 1 the float32 sweeps of the mixed solve)
+    // algorithmic bytes (matrix-free interior rows): per active row x read
+    // and written and b read, the nine coefficients of a stored row; a fused
+    // prolongation also reads x_c (class 0 float64, class 1 the float32
+    // sweeps of the mixed solve).  The flag byte per node is not counted.
+    // Every launch is idempotent (it reads one iterate buffer and writes the
+    // other), so a profiled launch may be repeated back to back.
     constexpr double vb = (double)sizeof(T);
-    double bytes = (3.0 * vb + 1.0) * L.n_active + 9.0 * vb * L.n_stored;
+    double bytes = 3.0 * vb * L.n_active + 9.0 * vb * L.n_stored;
     if (prolong_from) bytes += vb * c->lv[l + 1].n_active;
     prof_launch(c, std::is_same<T, double>::value ? 0 : 1, bytes, [a](hipStream_t st) {
       hipLaunchKernelGGL((k_sweep<T, TW, TH, BS>), dim3(8 * a.per), dim3(BS), 0, st, a);

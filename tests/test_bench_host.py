@@ -28,14 +28,21 @@ def test_committed_counters_match_the_sources():
     with open(bench.TRAFFIC_FILE) as fh:
         t = json.load(fh)
     assert t["kernel"] == bench.SWEEP_KERNEL
-    assert bench.measured_traffic("flower", 4096) == (
-        t["bytes_per_launch"] if t["source_hash"] == bench.source_hash() else None)
+    for rec in t["records"]:
+        w = rec["workload"]
+        assert bench.measured_traffic(w["domain"], w["N"]) == (
+            rec["bytes_per_launch"] if t["source_hash"] == bench.source_hash() else None)
 
 
-def test_counters_of_another_workload_give_no_traffic():
+def test_counters_of_another_workload_give_no_traffic(monkeypatch, tmp_path):
     with open(bench.TRAFFIC_FILE) as fh:
         t = json.load(fh)
-    assert t["workload"] == {"domain": "flower", "N": 4096}
+    t["source_hash"] = bench.source_hash()
+    t["records"] = [{"workload": {"domain": "flower", "N": 4096}, "bytes_per_launch": 1.0}]
+    p = tmp_path / "traffic.json"
+    p.write_text(json.dumps(t))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.measured_traffic("flower", 4096) == 1.0
     assert bench.measured_traffic("flower", 16384) is None
     assert bench.measured_traffic("ellipse", 4096) is None
 

@@ -93,6 +93,19 @@ def test_profiled_replay_times_the_sweep():
     # three finest sweeps per cycle plus the speculative one of the last iteration
     assert prof["launches"] == 3 * cycles + 1
     assert prof["total_ms"] > 0 and prof["alg_bytes"] > 0
+    # each timed launch repeated back to back: the same solve, one count per
+    # launch, the alg. bytes of the matrix-free count (24 B per active row,
+    # 72 B per stored row, 8 B per active coarse row with the prolongation)
+    s.profile(True, repeat=5)
+    u2, h2 = s.solve(p.f, p.g, tol=1e-10)
+    prof5 = s.profile_read(0)
+    s.profile(False)
+    assert np.array_equal(h0, h2) and torch.equal(u0, u2)
+    assert prof5["launches"] == prof["launches"]
+    assert prof5["alg_bytes"] == prof["alg_bytes"]
+    c0, c1 = s.level_counts(0), s.level_counts(1)
+    expect = prof["launches"] * (24 * c0["n_active"] + 72 * c0["n_stored"]) + cycles * 8 * c1["n_active"]
+    assert prof["alg_bytes"] == pytest.approx(expect, rel=1e-12)
 
 
 def test_mixed_loop_queued_iteration_is_discarded():

@@ -339,3 +339,24 @@ def test_residual_l2_history_matches_oracle():
     l2m = sm.residual_l2()
     assert len(l2m) == len(hm) and l2m[0] == pytest.approx(ref.hist_l2[0], rel=1e-12)
     assert l2m[-1] <= 1e-9 * l2m[0]
+
+
+@pytest.mark.parametrize("reverse", [False, True], ids=["forward", "transposed"])
+def test_single_steps_on_the_levels_of_n1024(reverse):
+    """One smoothing step on levels 1-4 of the flower at N = 1024 (512 ... 64
+    cells per side: the 64 x 16 and 16 x 16 sweep tiles and the cut-vertex
+    groups of grids larger than the N = 128 case), from random data, against
+    the oracle's smoothing step."""
+    mg = _gpu()
+    p, d, H = oracle_for("flower", 1024)
+    s = mg.Solver(p.psi, 1024)
+    for level in (1, 2, 3, 4):
+        lv = H.levels[level]
+        rng = np.random.default_rng(10 + level)
+        x0 = rng.standard_normal(lv.A.shape[0]) * lv.active
+        b = rng.standard_normal(lv.A.shape[0]) * lv.active
+        xo = x0.copy()
+        omg.smoothing_step(lv, xo, b, 4, reverse=reverse)
+        xg = torch.tensor(x0, device="cuda:0")
+        s.smooth(level, xg, torch.tensor(b, device="cuda:0"), 1, reverse)
+        assert rel_max(xg.cpu().numpy(), xo) < 1e-13, level
