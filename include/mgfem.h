@@ -335,10 +335,16 @@ const char* mgfem_last_error(mgfem_handle h);
 
 /*
  * Batched form: `count` independent problems (different psi and N) solved
- * together.  Setup builds every hierarchy; the solve runs all problems'
- * cycles in one persistent cooperative launch per solve, with per-problem
- * convergence.  Parameters are shared by all problems; the whole boundary is
- * Dirichlet.
+ * together, float32 cycles inside float64 defect correction, with
+ * per-problem convergence.  Setup builds every hierarchy and times two ways
+ * of running the batch, keeping the faster (the autotuner): the tiled path,
+ * where each step of the cycle is one launch over the tiles (cut groups,
+ * coarse-map rows, ...) of every problem still iterating, with the kernels
+ * and results of the single-problem mixed solve; or one persistent launch
+ * whose workgroups take whole problems from a queue, with one of four
+ * footprint widths.  Parameters are shared by all problems; the whole
+ * boundary is Dirichlet.  MGFEM_BATCH_PATH=tiled or =persistent at set-up
+ * fixes the choice.
  *  psi_dev[i] : device (N[i]+1)^2 float64.  N[i] as in mgfem_setup.
  */
 int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32_t* N,
@@ -354,8 +360,9 @@ int mgfem_solve_batched(mgfem_handle h, const double* const* f_dev, const double
                         double rel_tol, int32_t max_cycles, double* const* u_dev,
                         double* res_hist_host, int32_t* n_cycles);
 
-/* Footprint width (nodes per row of a workgroup's 1024-thread footprint on a
- * colour sub-lattice) picked by the batched autotuner, or -1. */
+/* The batched autotuner's choice: 0 for the tiled path, else the footprint
+ * width (nodes per row of a workgroup's 1024-thread footprint on a colour
+ * sub-lattice) of the persistent kernel; -1 for a handle that is not batched. */
 int mgfem_batched_tile(mgfem_handle h);
 
 #ifdef __cplusplus

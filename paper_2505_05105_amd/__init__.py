@@ -278,11 +278,11 @@ class BatchedSolver:
 
     @property
     def tile(self):
-        """Footprint width chosen by the autotuner."""
+        """The autotuner's choice: 0 the tiled path, else the persistent kernel's footprint width."""
         return _lib.lib().mgfem_batched_tile(self.handle)
 
     def last_ms(self):
-        """Device time of the last batched solve (one persistent launch)."""
+        """Device time of the last batched solve."""
         inf = _lib.Info()
         _lib.check(_lib.lib().mgfem_query(self.handle, C.byref(inf)), self.handle)
         return inf.setup_ms

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmgfem.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["geometry.hip", "hierarchy.hip", "plan.hip", "smoother.hip", "cycle.hip", "batched.hip",
-           "stabilise.hip", "api.hip", "noalloc.hip"]
+           "stabilise.hip", "api.hip", "noalloc.hip", "team.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-munsafe-fp-atomics"]

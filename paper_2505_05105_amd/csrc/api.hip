@@ -345,10 +345,8 @@ int setup_impl(const double* psi_dev, const double* chi_dev, int32_t N, const mg
   if (rc != MGFEM_OK) return bail(rc);
   rc = build_cut_rows(c);
   if (rc != MGFEM_OK) return bail(rc);
-  if (!member) {  // batch members run their coarse levels inside the batched kernel
-    rc = build_coarse_map(c);
-    if (rc != MGFEM_OK) return bail(rc);
-  }
+  rc = build_coarse_map(c, member);  // batch members run forward float cycles only
+  if (rc != MGFEM_OK) return bail(rc);
   SETUP_TRY(hipStreamSynchronize(c->s));
   mgfem_info& I = c->info;
   I.N = N;
@@ -405,6 +403,7 @@ int mgfem_destroy(mgfem_handle h) {
   if (!h) return MGFEM_ERR_INVALID_ARG;
   for (mgfem_ctx* m : h->members) free_ctx(m);
   h->members.clear();
+  team_free(h);
   free_ctx(h);
   return MGFEM_OK;
 }

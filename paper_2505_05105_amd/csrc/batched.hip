@@ -2,11 +2,13 @@
 // behind one handle, solved in one persistent launch (see k_batched).
 //
 // Setup builds one mixed-precision hierarchy per problem with the single-
-// problem setup, then a table of per-problem layout records.  The footprint
-// width of the workgroup's colour-phase loops is picked by a small autotuner:
-// each candidate runs two cycles of the whole batch on zero data, the
-// fastest wins, and the choice is kept per (device, batch shape) in the
-// process and, when MGFEM_TUNE_CACHE names a file, in that file.
+// problem setup, then a table of per-problem layout records for the
+// persistent kernel and the tables of the tiled path (team.hip).  A small
+// autotuner picks how the batch runs: the tiled path, or the persistent
+// kernel with one of four footprint widths of its colour-phase loops; each
+// candidate runs two cycles of the whole batch on zero data, the fastest
+// wins, and the choice is kept per (device, batch shape) in the process and,
+// when MGFEM_TUNE_CACHE names a file, in that file.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -34,28 +36,30 @@ std::string tune_key(const std::vector<int>& Ns, const mgfem_params& p) {
   long long sum = 0;
   for (int n : Ns) sum += (long long)(n + 1) * (n + 1);
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s|count=%zu|nodes=%lld|eta=%d|nu=%d,%d", arch.c_str(), Ns.size(), sum, p.eta,
-                p.nu1, p.nu2);
+  std::snprintf(buf, sizeof buf, "%s|paths=2|count=%zu|nodes=%lld|eta=%d|nu=%d,%d", arch.c_str(), Ns.size(), sum,
+                p.eta, p.nu1, p.nu2);
   return buf;
 }
 
+// the cached choice for this batch shape: 0 the tiled path, > 0 the
+// persistent kernel's footprint width, -1 none yet
 int cache_lookup(const std::string& key) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tune.find(key);
   if (it != g_tune.end()) return it->second;
   const char* path = std::getenv("MGFEM_TUNE_CACHE");
-  if (!path) return 0;
+  if (!path) return -1;
   FILE* fh = std::fopen(path, "r");
-  if (!fh) return 0;
+  if (!fh) return -1;
   char line[512];
-  int found = 0;
+  int found = -1;
   while (std::fgets(line, sizeof line, fh)) {
     char k[400];
     int tx;
-    if (std::sscanf(line, "%399s %d", k, &tx) == 2 && key == k) found = tx;
+    if (std::sscanf(line, "%399s %d", k, &tx) == 2 && key == k && tx >= 0) found = tx;
   }
   std::fclose(fh);
-  if (found) g_tune[key] = found;
+  if (found >= 0) g_tune[key] = found;
   return found;
 }
 
@@ -94,6 +98,7 @@ int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32
   b->s = reinterpret_cast<hipStream_t>(stream);
   auto bail = [&](int code, const std::string& msg) {
     free_batch(b);
+    team_free(b);
     for (void* q : b->allocs) (void)hipFree(q);
     delete b;
     set_setup_error(msg);
@@ -139,11 +144,22 @@ int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32
   BTRY(ctx_alloc_t(b, &d.ncyc, count));
   BTRY(ctx_alloc_t(b, &d.queue, 1));
   BTRY(hipStreamSynchronize(b->s));
-  // autotune the footprint width: two cycles of the whole batch on zero data
+  {
+    const int rc = team_build(b);
+    if (rc != MGFEM_OK) return bail(rc, "tiled batch path: " + b->last_error);
+  }
+  // autotune: the tiled path (all problems' tiles of one step per launch) or
+  // the persistent kernel with one of four footprint widths, each timed over
+  // two cycles of the whole batch on zero data
+  // MGFEM_BATCH_PATH=tiled or =persistent at set-up fixes the choice (tests)
+  const char* path_env = std::getenv("MGFEM_BATCH_PATH");
+  const std::string forced = path_env ? path_env : "";
   std::vector<int> Ns(N, N + count);
   const std::string key = tune_key(Ns, p);
-  d.tx = cache_lookup(key);
-  if (d.tx == 0) {
+  d.tx = forced.empty() ? cache_lookup(key) : -1;
+  if (d.tx == 0 && !team_ok(b)) d.tx = -1;
+  if (forced == "tiled" && team_ok(b)) d.tx = 0;
+  if (d.tx < 0) {
     std::vector<const double*> zf(count);
     std::vector<double*> scratch(count);
     for (int i = 0; i < count; ++i) {
@@ -166,7 +182,20 @@ int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32
         d.tx = tx;
       }
     }
-    cache_store(key, d.tx);
+    if (team_ok(b) && forced != "persistent") {
+      std::vector<double> th;
+      std::vector<int> tn;
+      float ms = 0.f;
+      for (int rep = 0; rep < 2; ++rep) {  // warm, then timed
+        const int rc = team_solve(b, zf.data(), zf.data(), scratch.data(), -1.0, cyc, th, tn, &ms);
+        if (rc != MGFEM_OK) return bail(rc, "tiled batch path: " + b->last_error);
+      }
+      if (ms < best) {
+        best = ms;
+        d.tx = 0;
+      }
+    }
+    if (forced.empty()) cache_store(key, d.tx);
   }
 #undef BTRY
   *out = b;
@@ -187,17 +216,24 @@ int mgfem_solve_batched(mgfem_handle b, const double* const* f_dev, const double
     MGFEM_HIP_TRY(ctx_alloc_t(b, &d.hist, (size_t)count * (max_cycles + 1)));
     d.hist_cap = max_cycles + 1;
   }
-  MGFEM_HIP_TRY(hipMemcpyAsync(d.f, f_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
-  MGFEM_HIP_TRY(hipMemcpyAsync(d.g, g_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
-  MGFEM_HIP_TRY(hipMemcpyAsync(d.u, u_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
-  const float ms = launch_batched(b, d, count, rel_tol, max_cycles, d.tx);
-  MGFEM_HIP_TRY(hipGetLastError());
-  b->info.setup_ms = ms;  // device time of the last batched solve
   std::vector<double> hist((size_t)count * (max_cycles + 1));
   std::vector<int> nc(count);
-  MGFEM_HIP_TRY(hipMemcpyAsync(hist.data(), d.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, b->s));
-  MGFEM_HIP_TRY(hipMemcpyAsync(nc.data(), d.ncyc, count * sizeof(int), hipMemcpyDeviceToHost, b->s));
-  MGFEM_HIP_TRY(hipStreamSynchronize(b->s));
+  if (d.tx == 0 && team_ok(b)) {
+    float ms = 0.f;
+    const int rc = team_solve(b, f_dev, g_dev, u_dev, rel_tol, max_cycles, hist, nc, &ms);
+    if (rc != MGFEM_OK) return rc;
+    b->info.setup_ms = ms;  // device time of the last batched solve
+  } else {
+    MGFEM_HIP_TRY(hipMemcpyAsync(d.f, f_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+    MGFEM_HIP_TRY(hipMemcpyAsync(d.g, g_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+    MGFEM_HIP_TRY(hipMemcpyAsync(d.u, u_dev, count * sizeof(void*), hipMemcpyHostToDevice, b->s));
+    const float ms = launch_batched(b, d, count, rel_tol, max_cycles, d.tx);
+    MGFEM_HIP_TRY(hipGetLastError());
+    b->info.setup_ms = ms;  // device time of the last batched solve
+    MGFEM_HIP_TRY(hipMemcpyAsync(hist.data(), d.hist, hist.size() * sizeof(double), hipMemcpyDeviceToHost, b->s));
+    MGFEM_HIP_TRY(hipMemcpyAsync(nc.data(), d.ncyc, count * sizeof(int), hipMemcpyDeviceToHost, b->s));
+    MGFEM_HIP_TRY(hipStreamSynchronize(b->s));
+  }
   bool all = true;
   for (int i = 0; i < count; ++i) {
     const double* h = hist.data() + (size_t)i * (max_cycles + 1);

@@ -591,6 +591,214 @@ __global__ void k_export(double* __restrict__ dst, const double* __restrict__ sr
 }
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Level-0 kernels of batched solves: one TeamL0 entry per problem, work items
+// (problem, block).  The arithmetic is that of k_cut_rows, k_rhs, k_outer and
+// k_export above.
+// ---------------------------------------------------------------------------
+namespace {
+
+// per-block (max, sum) into out[0], out[1]
+__device__ inline void block_pair_to(double mx, double sm, double* __restrict__ out) {
+  __shared__ double smax[4], ssum[4];
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = nanmax(mx, __shfl_xor(mx, o));
+    sm += __shfl_xor(sm, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smax[threadIdx.x >> 6] = mx;
+    ssum[threadIdx.x >> 6] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      mx = nanmax(mx, smax[w]);
+      sm += ssum[w];
+    }
+    out[0] = mx;
+    out[1] = sm;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_team_cut_rows(const TeamL0* __restrict__ tab, const int2* __restrict__ work,
+                                                       int nwork) {
+  if ((int)blockIdx.x >= nwork) return;
+  const int2 w = work[blockIdx.x];
+  const TeamL0& e = tab[w.x];
+  const int t = w.y * 256 + threadIdx.x;
+  if (t >= e.ncut) return;
+  const int N = e.N, s = e.s;
+  const int64_t k = e.cut_list[t];
+  const int i = (int)(k % s), j = (int)(k / s);
+  const double* r = e.cut_rows + 18 * (int64_t)t;
+  double acc = 0.0;
+  for (int p = 0; p < 9; ++p) {
+    const int ii = i + p % 3 - 1, jj = j + p / 3 - 1;
+    if (ii < 0 || jj < 0 || ii > N || jj > N) continue;
+    const int64_t kk = ii + (int64_t)jj * s;
+    const double m = r[p], gg = r[9 + p];
+    if (m != 0.0) acc += m * e.f[kk];
+    if (gg != 0.0) acc += gg * e.g[kk];
+  }
+  e.F[k] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_team_rhs(const TeamL0* __restrict__ tab, const int2* __restrict__ work,
+                                                  int nwork) {
+  __shared__ double sv[kSN];
+  if ((int)blockIdx.x >= nwork) return;
+  const int2 w = work[blockIdx.x];
+  const TeamL0& e = tab[w.x];
+  const int N = e.N, s = e.s;
+  const int bi = e.i0 + (w.y % e.gx) * kBX, bj = e.j0 + (w.y / e.gx) * kBY;
+  const double* f = e.f;
+  stage_box(sv, bi, bj, N, s, [&](int64_t k) { return f[k]; });
+  double mx = 0.0, sm = 0.0;
+  const int i = bi + threadIdx.x;
+#pragma unroll
+  for (int rep = 0; rep < kBY; ++rep) {
+    const int j = bj + rep;
+    if (i >= e.i0 + e.ni || j >= e.j0 + e.nj) continue;
+    const int64_t k = i + (int64_t)j * s;
+    const uint8_t fk = e.fl[k];
+    double acc = 0.0;
+    if (fk & kFlagActive) {
+      if (!(fk & kFlagStored)) acc = mass_row(sv, threadIdx.x + 1 + (rep + 1) * kSW, e.h36);
+      else if (fk & kFlagCut) acc = e.F[k];  // from k_team_cut_rows
+      else acc = plane_row(e.M, f, e.n, k, i, j, N, s) + plane_row(e.G, e.g, e.n, k, i, j, N, s);
+    }
+    if (!(fk & kFlagActive) || !(fk & kFlagStored) || !(fk & kFlagCut)) e.F[k] = acc;
+    mx = nanmax(mx, fabs(acc));
+    sm += acc * acc;
+  }
+  block_pair_to(mx, sm, e.part + 2 * w.y);
+}
+
+// first = 1: the step from u = 0 (r = F; u's buffer 0 set to 0 on the active
+// nodes); else u_new = U[upar] + E[epar] into U[1 - upar]
+__global__ __launch_bounds__(256) void k_team_outer(const TeamL0* __restrict__ tab, const int2* __restrict__ work,
+                                                    int nwork, int upar, int epar, int first) {
+  __shared__ double sv[kSN];
+  if ((int)blockIdx.x >= nwork) return;
+  const int2 w = work[blockIdx.x];
+  const TeamL0& e = tab[w.x];
+  const int bi = e.i0 + (w.y % e.gx) * kBX, bj = e.j0 + (w.y / e.gx) * kBY;
+  const double* u = e.U[upar];
+  const float* ev = e.E[epar];
+  if (first) stage_box(sv, bi, bj, e.N, e.s, [&](int64_t) { return 0.0; });
+  else stage_box(sv, bi, bj, e.N, e.s, [&](int64_t k) { return u[k] + (double)ev[k]; });
+  double* u_out = first ? e.U[0] : e.U[1 - upar];
+  float* z32 = first ? e.E[0] : e.E[1 - epar];
+  double mx = 0.0, sm = 0.0;
+  const int i = bi + threadIdx.x;
+#pragma unroll
+  for (int rep = 0; rep < kBY; ++rep) {
+    const int j = bj + rep;
+    if (i >= e.i0 + e.ni || j >= e.j0 + e.nj) continue;
+    const int64_t k = i + (int64_t)j * e.s;
+    const uint8_t f = e.fl[k];
+    if (!(f & kFlagActive)) continue;
+    const int q = threadIdx.x + 1 + (rep + 1) * kSW;
+    const double uk = sv[q];
+    const double ax = (f & kFlagStored) ? box_row(e.A, e.n, k, sv, q)
+                                        : 8.0 / 3.0 * uk - box_neighbours(sv, q) * (1.0 / 3.0);
+    const double r = e.F[k] - ax;
+    u_out[k] = uk;
+    e.r32[k] = (float)r;
+    z32[k] = 0.0f;
+    mx = nanmax(mx, fabs(r));
+    sm += r * r;
+  }
+  block_pair_to(mx, sm, e.part + 2 * w.y);
+}
+
+__global__ __launch_bounds__(256) void k_team_export(const TeamL0* __restrict__ tab, const int2* __restrict__ work,
+                                                     int nwork) {
+  if ((int)blockIdx.x >= nwork) return;
+  const int2 w = work[blockIdx.x];
+  const TeamL0& e = tab[w.x];
+  const int64_t k = w.y * (int64_t)256 + threadIdx.x;
+  if (k >= e.n) return;
+  const int i = (int)(k % e.s), j = (int)(k / e.s);
+  const bool in = i >= e.i0 && i < e.i0 + e.ni && j >= e.j0 && j < e.j0 + e.nj;
+  e.u_out[k] = in ? e.U[e.ucur][k] : 0.0;
+}
+
+// one workgroup per listed problem: its box partials in block order
+__global__ __launch_bounds__(256) void k_team_reduce(const TeamL0* __restrict__ tab, const int* __restrict__ probs,
+                                                     double* __restrict__ out) {
+  const int p = probs[blockIdx.x];
+  const TeamL0& e = tab[p];
+  double mx = 0.0, sm = 0.0;
+  for (int q = threadIdx.x; q < e.nb; q += blockDim.x) {
+    mx = nanmax(mx, e.part[2 * q]);
+    sm += e.part[2 * q + 1];
+  }
+  block_pair_to(mx, sm, out + 2 * p);
+}
+
+}  // namespace
+
+void team_l0_entry(mgfem_ctx* m, TeamL0* out) {
+  const Level& L = m->lv[0];
+  TeamL0 e{};
+  e.A = L.A;
+  e.fl = L.flags;
+  e.N = L.N;
+  e.s = L.stride;
+  e.n = L.n;
+  e.M = m->M;
+  e.G = m->G;
+  e.h36 = m->h * m->h / 36.0;
+  e.cut_list = L.cut_list;
+  e.ncut = L.cut_off[4];
+  e.cut_rows = m->cut_rows;
+  e.F = m->F;
+  e.U[0] = m->x0;
+  e.U[1] = L.X[1];
+  e.E[0] = L.X32[0];
+  e.E[1] = L.X32[1];
+  e.r32 = L.b32;
+  e.i0 = L.bbox[0];
+  e.j0 = L.bbox[2];
+  e.ni = std::max(0, L.bbox[1] - L.bbox[0] + 1);
+  e.nj = std::max(0, L.bbox[3] - L.bbox[2] + 1);
+  e.gx = std::max(1, (e.ni + kBX - 1) / kBX);
+  e.nb = e.gx * std::max(1, (e.nj + kBY - 1) / kBY);
+  e.part = m->red_partial;
+  *out = e;
+}
+
+int team_l0_units(const TeamL0& e, int kind) {
+  switch (kind) {
+    case kTeamCutRows: return (e.ncut + 255) / 256;
+    case kTeamRhs:
+    case kTeamOuterFirst:
+    case kTeamOuter: return e.ni > 0 && e.nj > 0 ? e.nb : 0;
+    case kTeamExport: return (int)((e.n + 255) / 256);
+  }
+  return 0;
+}
+
+void team_l0_launch(hipStream_t s, int kind, const TeamL0* tab, const int2* work, int nwork, int upar, int epar) {
+  if (nwork <= 0) return;
+  switch (kind) {
+    case kTeamCutRows: hipLaunchKernelGGL(k_team_cut_rows, dim3(nwork), dim3(256), 0, s, tab, work, nwork); break;
+    case kTeamRhs: hipLaunchKernelGGL(k_team_rhs, dim3(nwork), dim3(256), 0, s, tab, work, nwork); break;
+    case kTeamOuterFirst:
+      hipLaunchKernelGGL(k_team_outer, dim3(nwork), dim3(256), 0, s, tab, work, nwork, 0, 0, 1);
+      break;
+    case kTeamOuter:
+      hipLaunchKernelGGL(k_team_outer, dim3(nwork), dim3(256), 0, s, tab, work, nwork, upar, epar, 0);
+      break;
+    case kTeamExport: hipLaunchKernelGGL(k_team_export, dim3(nwork), dim3(256), 0, s, tab, work, nwork); break;
+  }
+}
+
+void team_reduce(hipStream_t s, const TeamL0* tab, const int* probs, int nprobs, double* out) {
+  if (nprobs > 0) hipLaunchKernelGGL(k_team_reduce, dim3(nprobs), dim3(256), 0, s, tab, probs, out);
+}
+
 void launch_box_copy(mgfem_ctx* c, double* dst, const double* src) {
   const Level& L = c->lv[0];
   const int ni = L.bbox[1] - L.bbox[0] + 1, nj = L.bbox[3] - L.bbox[2] + 1;

@@ -212,6 +212,61 @@ struct Stats {
   unsigned long long dirichlet_cells;  // cut cells with a Dirichlet segment
 };
 
+// Batched solves on the tiled kernels ("team" path, team.hip): every launch
+// covers the same step of the cycle for all problems of the batch, its
+// workgroups taking (problem, unit) items of a work list.  Level-0 entry of
+// one problem (plain device pointers; the data pointers change per solve).
+struct TeamL0 {
+  const double* A;
+  const uint8_t* fl;
+  int N, s;
+  int64_t n;
+  const double* M;
+  const double* G;
+  double h36;                // h^2 / 36, the interior mass stencil's scale
+  const int* cut_list;
+  int ncut;
+  const double* cut_rows;    // 18 per cut-cell vertex: M row, G row
+  double* F;                 // the load vector (level-0 right-hand side)
+  double* U[2];              // float64 iterate buffers
+  float* E[2];               // level-0 float iterates of the inner cycles
+  float* r32;                // float residual: the inner cycle's right-hand side
+  int i0, j0, ni, nj, gx;    // box of active nodes; 256 x 4 blocks per box row
+  int nb;                    // blocks of the box (gx times the rows of blocks)
+  double* part;              // one (max, sum) pair per box block
+  const double* f;           // this solve's data and output
+  const double* g;
+  double* u_out;
+  int ucur;                  // buffer of U that holds the final iterate (export)
+};
+constexpr int kTeamSweep = 0, kTeamCut = 1, kTeamRR = 2, kTeamMap = 3;  // float-cycle launch kinds
+constexpr int kTeamCutRows = 0, kTeamRhs = 1, kTeamOuterFirst = 2, kTeamOuter = 3, kTeamExport = 4;
+// float cycle (smoother.hip): entry size, one member's entry at level l,
+// its work units there (-1: the member cannot take this path), one launch
+size_t team_entry_bytes(int kind);
+void team_entry(mgfem_ctx* m, int kind, int l, void* out);
+int team_units(mgfem_ctx* m, int kind, int l);
+int team_lds(mgfem_ctx* m, int kind, int l);  // dynamic LDS of its units
+void team_launch(hipStream_t s, int kind, const void* tab, const int2* work, int nwork, int par, int parc,
+                 int prolong, int lds);
+// level 0 (cycle.hip): a member's entry (data pointers left null), the units
+// of a level-0 launch kind, one launch, and the per-problem reduction of the
+// box partials into out[2 p], out[2 p + 1] (max, sum of squares)
+void team_l0_entry(mgfem_ctx* m, TeamL0* out);
+int team_l0_units(const TeamL0& e, int kind);
+void team_l0_launch(hipStream_t s, int kind, const TeamL0* tab, const int2* work, int nwork, int upar, int epar);
+void team_reduce(hipStream_t s, const TeamL0* tab, const int* probs, int nprobs, double* out);
+// the tiled path of a batched handle (team.hip): tables after the members'
+// set-up, one solve (history count x (max_cycles + 1), cycles per problem,
+// device time of the solve), release
+int team_build(mgfem_ctx* b);
+bool team_ok(const mgfem_ctx* b);
+int team_solve(mgfem_ctx* b, const double* const* f, const double* const* g, double* const* u, double rel_tol,
+               int max_cycles, std::vector<double>& hist, std::vector<int>& ncyc, float* ms);
+void team_free(mgfem_ctx* b);
+
+struct TeamPlan;  // team.hip
+
 struct BatchDevice {
   void* probs = nullptr;  // per-problem layout records (built in smoother.hip)
   int* order = nullptr;   // problems by decreasing size (work-queue order)
@@ -285,6 +340,7 @@ struct mgfem_ctx {
   bool batched_member = false;
   std::vector<mgfem_ctx*> members;  // batched handle: one context per problem
   mgfem::BatchDevice batch;
+  mgfem::TeamPlan* team = nullptr;  // batched handle: the tiled path's tables (null or !ok: not available)
 };
 
 namespace mgfem {
@@ -359,14 +415,14 @@ void run_cycle(mgfem_ctx* c, const CycleOpts& o);
 void smooth_level(mgfem_ctx* c, int l, bool reverse, bool fp32);
 void gather_snap(mgfem_ctx* c, int l, bool fp32);
 int build_plans(mgfem_ctx* c);  // cut groups and the coarse single-workgroup layout
-// the coarse part as a dense map (forward and transposed, float64; float32
-// forward for mixed precision); skipped for batch members and large first
-// coarse levels, and when MGFEM_NO_COARSE_MAP=1 at set-up
-int build_coarse_map(mgfem_ctx* c);
+// the coarse part as a dense map (forward and, unless forward_only, transposed,
+// float64; float32 forward for mixed precision); skipped for large first
+// coarse levels and when MGFEM_NO_COARSE_MAP=1 at set-up
+int build_coarse_map(mgfem_ctx* c, bool forward_only);
 // the device-side address of the static scratch array of the current device,
 // looked up once per device (noalloc.hip); *device receives that device
 int scratch_init(int* device);
-// mgfem_setup for one problem of a batched handle (no coarse map)
+// mgfem_setup for one problem of a batched handle (forward coarse map only)
 int setup_member(const double* psi_dev, int32_t N, const mgfem_params* p, void* stream, mgfem_handle* out);
 int build_tile_lists(mgfem_ctx* c);
 // sweep tile shapes, all with 512 threads (a workgroup's load phase is bound

@@ -166,8 +166,9 @@ __device__ inline void lds_load16(const void* src, void* dst) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
 }
 
+// the sweep of tile t of the level's tile list (one workgroup)
 template <class T, int TW, int TH, int BS>
-__global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
+__device__ void sweep_tile(const SweepArgs<T>& a, const int t) {
   constexpr int RW = TW + 2 * kHalo, RH = TH + 2 * kHalo;
   constexpr int NU = (RW * RH + BS - 1) / BS;
   constexpr int NXM = (RW - 1) / 2, NYM = (RH - 1) / 2;  // colour nodes per row/column, phase 0 bound
@@ -186,9 +187,6 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   __shared__ __align__(16) T sxc[NCCH * 64 * G];
   __shared__ T scf[9 * PR];
   __shared__ uint8_t sslot[RH * RW];  // stored node: its row in scf (255: read A); others unused
-  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
-  const int t = xcd * a.per + loc;
-  if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
   // tile, plan offsets and counts in one uniform 32-byte load
   const int* mt = a.tmeta + 8 * t;
   const int tile = mt[0], p0 = mt[1], nrow = mt[2], c0 = mt[3], ncut = mt[4];
@@ -387,6 +385,46 @@ __global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
   for (int e = tid + KC * BS; e < ncut; e += BS) a.snap[a.tc_pos[c0 + e]] = su[a.tc_idx[c0 + e]];
 }
 
+// Work lists of a launch are dealt to the eight XCDs in contiguous eighths
+// (workgroups are dealt to the XCDs round robin), so that neighbouring tiles
+// of one level share an XCD's L2.
+__device__ inline int xcd_item(int per) { return (blockIdx.x & 7) * per + (blockIdx.x >> 3); }
+
+template <class T, int TW, int TH, int BS>
+__global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
+  const int t = xcd_item(a.per);
+  if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
+  sweep_tile<T, TW, TH, BS>(a, t);
+}
+
+// Several problems in one launch (batched solves): one entry per problem
+// with the arguments of its level and both ping-pong buffers of the level
+// and of the next coarser one; the work list holds (problem, tile) pairs.
+// par is the level's parity (which buffer holds the iterate), parc that of
+// the coarser level, except for problems whose coarser level is the first
+// level of their coarse part (its iterate is always buffer 0).
+template <class T>
+struct SweepEntry {
+  SweepArgs<T> a;
+  T* X[2];
+  const T* XC[2];
+  int xc_fixed;
+};
+
+template <class T, int TW, int TH, int BS>
+__global__ __launch_bounds__(BS) void k_sweep_multi(const SweepEntry<T>* tab, const int2* work, int nwork,
+                                                    int par, int parc, int prolong) {
+  const int i = xcd_item((nwork + 7) >> 3);
+  if (i >= nwork) return;
+  const int2 w = work[i];
+  const SweepEntry<T>& E = tab[w.x];
+  SweepArgs<T> a = E.a;
+  a.xin = E.X[par];
+  a.xout = E.X[1 - par];
+  a.xc = prolong ? E.XC[E.xc_fixed ? 0 : parc] : nullptr;
+  sweep_tile<T, TW, TH, BS>(a, w.y);
+}
+
 // extra smoothing of one group of cut vertices, all phases in LDS
 template <class T>
 struct CutArgs {
@@ -408,10 +446,11 @@ struct alignas(16) Refs8 {
   int16_t r[8];
 };
 
+// the eta sweeps of cut group g (one workgroup of 256 threads; smem: the
+// group's dynamic LDS)
 template <class T>
-__global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int* gi = a.g_info + 9 * blockIdx.x;
+__device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem) {
+  const int* gi = a.g_info + 9 * g;
   const int cl_off = gi[0], cl_cnt = gi[1], ext_off = gi[2], ext_cnt = gi[3];
   const CutLds lay = cut_lds_layout(cl_cnt, ext_cnt, (int)sizeof(T));
   T* vals = reinterpret_cast<T*>(smem + lay.vals);
@@ -526,6 +565,30 @@ __global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
     if (a.cl_own[cl_off + t]) a.x[a.cl_node[cl_off + t]] = vals[t];
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  cut_group<T>(a, blockIdx.x, smem);
+}
+
+template <class T>
+struct CutEntry {
+  CutArgs<T> a;
+  T* X[2];
+};
+
+template <class T>
+__global__ __launch_bounds__(256) void k_cut_multi(const CutEntry<T>* tab, const int2* work, int nwork, int par) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int i = xcd_item((nwork + 7) >> 3);
+  if (i >= nwork) return;
+  const int2 w = work[i];
+  const CutEntry<T>& E = tab[w.x];
+  CutArgs<T> a = E.a;
+  a.x = E.X[par];
+  cut_group<T>(a, w.y, smem);
+}
+
 // one colour phase over a list of nodes (used when a level has no group plan)
 template <class T>
 __global__ void k_gs_list(const T* __restrict__ A, const uint8_t* __restrict__ fl, T* x, const T* __restrict__ b,
@@ -573,16 +636,14 @@ __device__ inline T row_product(const T* __restrict__ A, int64_t n, int64_t k, b
   return T(8) / T(3) * su[q] - q1_neighbours<T, RW>(su, q) * T(1.0 / 3.0);
 }
 
+// residual and restriction of coarse tile t of the level's list
 template <class T, int CW, int CH, int BS>
-__global__ __launch_bounds__(BS) void k_resrestrict(ResArgs<T> a) {
+__device__ void rr_tile(const ResArgs<T>& a, const int t) {
   constexpr int RW = 2 * CW + 1, RH = 2 * CH + 1;  // fine residual region
   constexpr int UW = RW + 2, UH = RH + 2;          // fine x region
   constexpr int NU = (UW * UH + BS - 1) / BS, NR = (RW * RH + BS - 1) / BS;
   __shared__ T su[UH * UW];
   __shared__ T sr[RH * RW];
-  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
-  const int t = xcd * a.per + loc;
-  if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
   const int tile = a.tiles[t];
   const int tid = threadIdx.x;
   const int tx = tile % a.ntx, ty = tile / a.ntx;
@@ -646,6 +707,34 @@ __global__ __launch_bounds__(BS) void k_resrestrict(ResArgs<T> a) {
     a.xc[kc] = T(0);
     if (f & kFlagCut) a.snapc[a.cutposc[kc]] = T(0);
   }
+}
+
+template <class T, int CW, int CH, int BS>
+__global__ __launch_bounds__(BS) void k_resrestrict(ResArgs<T> a) {
+  const int t = xcd_item(a.per);
+  if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
+  rr_tile<T, CW, CH, BS>(a, t);
+}
+
+template <class T>
+struct RrEntry {
+  ResArgs<T> a;
+  const T* X[2];
+  T* XC[2];
+  int xc_fixed;
+};
+
+template <class T, int CW, int CH, int BS>
+__global__ __launch_bounds__(BS) void k_resrestrict_multi(const RrEntry<T>* tab, const int2* work, int nwork,
+                                                          int par, int parc) {
+  const int i = xcd_item((nwork + 7) >> 3);
+  if (i >= nwork) return;
+  const int2 w = work[i];
+  const RrEntry<T>& E = tab[w.x];
+  ResArgs<T> a = E.a;
+  a.x = E.X[par];
+  a.xc = E.XC[E.xc_fixed ? 0 : parc];
+  rr_tile<T, CW, CH, BS>(a, w.y);
 }
 
 template <class T>
@@ -1064,17 +1153,25 @@ struct Vec16<float> {
 constexpr int kMapWaves = 4;  // rows of B per 256-thread workgroup
 
 template <class T>
-__global__ __launch_bounds__(64 * kMapWaves) void k_coarse_apply(const T* __restrict__ B, int ld,
-                                                                 const int* __restrict__ idx, int n,
-                                                                 const T* __restrict__ b, T* __restrict__ x) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* sb = reinterpret_cast<T*>(smem);
+struct MapEntry {
+  const T* B;
+  int ld;
+  const int* idx;
+  int n;
+  const T* b;
+  T* x;
+};
+
+// rows kMapWaves blk ... kMapWaves (blk + 1) - 1 of x = B b (sb: ld values of LDS)
+template <class T>
+__device__ void map_rows(const T* __restrict__ B, int ld, const int* __restrict__ idx, int n,
+                         const T* __restrict__ b, T* __restrict__ x, const int blk, T* sb) {
   using V = typename Vec16<T>::type;
   constexpr int G = 16 / (int)sizeof(T);  // values per 16-byte load
   constexpr int U = 8;                    // loads in flight per lane
   constexpr int CH = U * 64 * G;          // values of a row per round
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int r = blockIdx.x * kMapWaves + wave;
+  const int r = blk * kMapWaves + wave;
   const T* row = B + (int64_t)(r < n ? r : 0) * ld;
   V v[U];
   auto load = [&](int base) {
@@ -1100,6 +1197,25 @@ __global__ __launch_bounds__(64 * kMapWaves) void k_coarse_apply(const T* __rest
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0 && r < n) x[idx[r]] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(64 * kMapWaves) void k_coarse_apply(const T* __restrict__ B, int ld,
+                                                                 const int* __restrict__ idx, int n,
+                                                                 const T* __restrict__ b, T* __restrict__ x) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  map_rows<T>(B, ld, idx, n, b, x, blockIdx.x, reinterpret_cast<T*>(smem));
+}
+
+template <class T>
+__global__ __launch_bounds__(64 * kMapWaves) void k_coarse_apply_multi(const MapEntry<T>* tab, const int2* work,
+                                                                       int nwork) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int i = blockIdx.x;
+  if (i >= nwork) return;
+  const int2 w = work[i];
+  const MapEntry<T>& E = tab[w.x];
+  map_rows<T>(E.B, E.ld, E.idx, E.n, E.b, E.x, w.y, reinterpret_cast<T*>(smem));
 }
 
 __global__ void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d, int64_t n) {
@@ -1134,8 +1250,10 @@ double* Sp<double>(Level& L) { return L.snap; }
 template <>
 float* Sp<float>(Level& L) { return L.snap32; }
 
-template <class T, int TW, int TH, int BS>
-void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_from, int shape) {
+// arguments of the sweep of level l with TW x TH tiles from the level's
+// current state (ping-pong parities)
+template <class T, int TW, int TH>
+SweepArgs<T> sweep_args(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_from) {
   Level& L = c->lv[l];
   SweepArgs<T> a;
   a.part = c->sweep_part;
@@ -1167,7 +1285,6 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   // the shape sweep_shape() gives
   a.tiles = L.tiles;
   a.ntiles = L.ntiles;
-  (void)shape;
   a.per = (a.ntiles + 7) / 8;
   a.reverse = reverse ? 1 : 0;
   a.tmeta = L.tmeta;
@@ -1179,6 +1296,14 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   a.tc_idx = L.tc_idx;
   a.tc_pos = L.tc_pos;
   a.zero = reinterpret_cast<const T*>(c->zero);
+  return a;
+}
+
+template <class T, int TW, int TH, int BS>
+void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_from, int shape) {
+  Level& L = c->lv[l];
+  const SweepArgs<T> a = sweep_args<T, TW, TH>(c, l, reverse, norm, prolong_from);
+  (void)shape;
   if (c->prof.on && l == 0) {
     // algorithmic bytes (matrix-free interior rows): per active row x read
     // and written and b read, the nine coefficients of a stored row; a fused
@@ -1215,25 +1340,32 @@ void sweep(mgfem_ctx* c, int l, bool reverse, bool norm = false, bool prolong_fr
 }
 
 template <class T>
+CutArgs<T> cut_args(mgfem_ctx* c, int l, bool reverse) {
+  Level& L = c->lv[l];
+  CutArgs<T> a;
+  a.g_info = L.cp.g_info;
+  a.cl_node = L.cp.cl_node;
+  a.cl_q = L.cp.cl_q;
+  a.cl_own = L.cp.cl_own;
+  a.cl_nbr = L.cp.cl_nbr;
+  a.ext_src = L.cp.ext_src;
+  a.cl_coef = std::is_same<T, double>::value ? reinterpret_cast<const T*>(L.cp.cl_coef)
+                                             : reinterpret_cast<const T*>(L.cp.cl_coef32);
+  a.x = Xp<T>(L, L.cur);
+  a.b = Bp<T>(L);
+  a.snap = Sp<T>(L);
+  a.eta = c->p.eta;
+  a.reverse = reverse ? 1 : 0;
+  return a;
+}
+
+template <class T>
 void cut_sweeps(mgfem_ctx* c, int l, bool reverse) {
   Level& L = c->lv[l];
   const int eta = c->p.eta;
   if (eta == 0 || L.cut_off[4] == 0) return;
   if (L.cp.ok) {
-    CutArgs<T> a;
-    a.g_info = L.cp.g_info;
-    a.cl_node = L.cp.cl_node;
-    a.cl_q = L.cp.cl_q;
-    a.cl_own = L.cp.cl_own;
-    a.cl_nbr = L.cp.cl_nbr;
-    a.ext_src = L.cp.ext_src;
-    a.cl_coef = std::is_same<T, double>::value ? reinterpret_cast<const T*>(L.cp.cl_coef)
-                                               : reinterpret_cast<const T*>(L.cp.cl_coef32);
-    a.x = Xp<T>(L, L.cur);
-    a.b = Bp<T>(L);
-    a.snap = Sp<T>(L);
-    a.eta = eta;
-    a.reverse = reverse ? 1 : 0;
+    const CutArgs<T> a = cut_args<T>(c, l, reverse);
     const size_t lds = std::is_same<T, double>::value ? L.cp.lds64 : L.cp.lds32;
     hipLaunchKernelGGL(k_cut<T>, dim3(L.cp.ngroups), dim3(256), lds, c->s, a);
     return;
@@ -1259,11 +1391,10 @@ void smooth(mgfem_ctx* c, int l, bool reverse) {
   }
 }
 
-template <class T, int CW, int CH, int BS>
-void launch_resrestrict(mgfem_ctx* c, int l) {
+template <class T, int CW, int CH>
+ResArgs<T> rr_args(mgfem_ctx* c, int l) {
   Level& L = c->lv[l];
   Level& C = c->lv[l + 1];
-  if (C.empty()) return;
   ResArgs<T> a;
   a.x = Xp<T>(L, L.cur);
   a.b = Bp<T>(L);
@@ -1287,8 +1418,16 @@ void launch_resrestrict(mgfem_ctx* c, int l) {
   a.nty = (a.J1 - a.J0 + CH) / CH;
   a.tiles = L.rr_tiles;
   a.ntiles = L.rr_ntiles;
-  if (a.ntiles == 0) return;
   a.per = (a.ntiles + 7) / 8;
+  return a;
+}
+
+template <class T, int CW, int CH, int BS>
+void launch_resrestrict(mgfem_ctx* c, int l) {
+  Level& L = c->lv[l];
+  Level& C = c->lv[l + 1];
+  if (C.empty() || L.rr_ntiles == 0) return;
+  const ResArgs<T> a = rr_args<T, CW, CH>(c, l);
   hipLaunchKernelGGL((k_resrestrict<T, CW, CH, BS>), dim3(8 * a.per), dim3(BS), 0, c->s, a);
 }
 
@@ -1405,6 +1544,122 @@ void run_cycle(mgfem_ctx* c, const CycleOpts& o) {
 }
 
 void first_sweep_with_norm(mgfem_ctx* c) { sweep<double>(c, 0, false, true); }
+
+// ---- batched solves on the tiled kernels: float-cycle entries and launches.
+// Every level a batch member smooths must use the small tile shapes (16 x 16
+// sweep tiles, 16 x 8 residual tiles) and have its cut groups; the first
+// level of its coarse part is applied with its float map.
+size_t team_entry_bytes(int kind) {
+  switch (kind) {
+    case kTeamSweep: return sizeof(SweepEntry<float>);
+    case kTeamCut: return sizeof(CutEntry<float>);
+    case kTeamRR: return sizeof(RrEntry<float>);
+    case kTeamMap: return sizeof(MapEntry<float>);
+  }
+  return 0;
+}
+
+void team_entry(mgfem_ctx* m, int kind, int l, void* out) {
+  Level& L = m->lv[l];
+  const bool fixed = m->cplan.lc == l + 1;  // the coarser level is the coarse map's level
+  switch (kind) {
+    case kTeamSweep: {
+      SweepEntry<float> e{};
+      e.a = sweep_args<float, 16, 16>(m, l, false, false, false);
+      e.a.sc = m->lv[l + 1].stride;
+      e.X[0] = L.X32[0];
+      e.X[1] = L.X32[1];
+      e.XC[0] = m->lv[l + 1].X32[0];
+      e.XC[1] = m->lv[l + 1].X32[1];
+      e.xc_fixed = fixed ? 1 : 0;
+      std::memcpy(out, &e, sizeof e);
+      break;
+    }
+    case kTeamCut: {
+      CutEntry<float> e{};
+      if (L.cp.ok) e.a = cut_args<float>(m, l, false);
+      e.X[0] = L.X32[0];
+      e.X[1] = L.X32[1];
+      std::memcpy(out, &e, sizeof e);
+      break;
+    }
+    case kTeamRR: {
+      RrEntry<float> e{};
+      e.a = rr_args<float, 16, 8>(m, l);
+      e.X[0] = L.X32[0];
+      e.X[1] = L.X32[1];
+      e.XC[0] = m->lv[l + 1].X32[0];
+      e.XC[1] = m->lv[l + 1].X32[1];
+      e.xc_fixed = fixed ? 1 : 0;
+      std::memcpy(out, &e, sizeof e);
+      break;
+    }
+    case kTeamMap: {
+      MapEntry<float> e{};
+      const CoarseMap& M = m->cplan.map;
+      Level& Lc = m->lv[m->cplan.lc];
+      e.B = M.f32;
+      e.ld = M.ld;
+      e.idx = M.idx;
+      e.n = M.n;
+      e.b = Lc.b32;
+      e.x = Lc.X32[0];
+      std::memcpy(out, &e, sizeof e);
+      break;
+    }
+  }
+}
+
+int team_units(mgfem_ctx* m, int kind, int l) {
+  Level& L = m->lv[l];
+  switch (kind) {
+    case kTeamSweep:
+      if (L.empty()) return 0;
+      return sweep_shape(m, l) == kShapeSmall ? L.ntiles : -1;
+    case kTeamCut:
+      if (m->p.eta == 0 || L.cut_off[4] == 0) return 0;
+      return L.cp.ok ? L.cp.ngroups : -1;
+    case kTeamRR:
+      if (m->lv[l + 1].empty()) return 0;
+      return L.N < 1024 ? L.rr_ntiles : -1;
+    case kTeamMap: {
+      const CoarseMap& M = m->cplan.map;
+      if (M.n <= 0) return 0;
+      return M.f32 && M.reps == 1 ? (M.n + kMapWaves - 1) / kMapWaves : -1;
+    }
+  }
+  return -1;
+}
+
+int team_lds(mgfem_ctx* m, int kind, int l) {
+  if (kind == kTeamCut) return m->lv[l].cp.lds32;
+  if (kind == kTeamMap) return m->cplan.map.ld * (int)sizeof(float);
+  return 0;
+}
+
+void team_launch(hipStream_t s, int kind, const void* tab, const int2* work, int nwork, int par, int parc,
+                 int prolong, int lds) {
+  if (nwork <= 0) return;
+  const unsigned grid = 8u * (unsigned)((nwork + 7) / 8);
+  switch (kind) {
+    case kTeamSweep:
+      hipLaunchKernelGGL((k_sweep_multi<float, 16, 16, 512>), dim3(grid), dim3(512), 0, s,
+                         static_cast<const SweepEntry<float>*>(tab), work, nwork, par, parc, prolong);
+      break;
+    case kTeamCut:
+      hipLaunchKernelGGL(k_cut_multi<float>, dim3(grid), dim3(256), lds, s, static_cast<const CutEntry<float>*>(tab),
+                         work, nwork, par);
+      break;
+    case kTeamRR:
+      hipLaunchKernelGGL((k_resrestrict_multi<float, 16, 8, 512>), dim3(grid), dim3(512), 0, s,
+                         static_cast<const RrEntry<float>*>(tab), work, nwork, par, parc);
+      break;
+    case kTeamMap:
+      hipLaunchKernelGGL(k_coarse_apply_multi<float>, dim3(nwork), dim3(64 * kMapWaves), lds, s,
+                         static_cast<const MapEntry<float>*>(tab), work, nwork);
+      break;
+  }
+}
 
 // tile activity of one level for its sweep shape: a tile is kept when its core
 // holds an active node (tiles entirely outside the domain are skipped)
@@ -1571,7 +1826,7 @@ int build_tile_lists(mgfem_ctx* c) {
   return MGFEM_OK;
 }
 
-int build_coarse_map(mgfem_ctx* c) {
+int build_coarse_map(mgfem_ctx* c, bool forward_only) {
   CoarsePlan& P = c->cplan;
   CoarseMap& M = P.map;
   if (P.lc < 0 || M.n <= 0 || M.n > kMaxMapNodes) return MGFEM_OK;
@@ -1586,7 +1841,7 @@ int build_coarse_map(mgfem_ctx* c) {
   M.reps = two_grid ? c->p.coarse_cycles : (c->p.cycle == MGFEM_CYCLE_W ? 2 : 1);
   M.ld = (M.n + 15) / 16 * 16;
   const size_t cnt = (size_t)M.ld * M.n;
-  for (int rev = 0; rev < 2; ++rev) {
+  for (int rev = 0; rev < (forward_only ? 1 : 2); ++rev) {
     MGFEM_HIP_TRY(ctx_alloc_t(c, &M.f64[rev], cnt));  // zeroed: the padding columns stay 0
     CoarseArgs<double> a = coarse_args<double>(c, rev != 0, M.reps);
     a.unit = 1;
@@ -1618,6 +1873,8 @@ void set_kernel_attributes() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cut<double>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cut<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cut_multi<float>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse<double>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -24,7 +24,7 @@ def test_batched_matches_oracle_per_problem():
     mg = _gpu()
     probs = W.batched_draws(count=8, seed=0, sizes=(32, 64, 128))
     bs = mg.BatchedSolver([p.psi for p in probs], [p.N for p in probs])
-    assert bs.tile in (32, 64, 128, 256)
+    assert bs.tile in (0, 32, 64, 128, 256)
     for tol in (1e-10, 1e-12):
         us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=tol, max_cycles=80)
         assert bs.last_status == 0
@@ -89,3 +89,54 @@ def test_single_problem_calls_reject_a_batched_handle():
     torch.cuda.synchronize()
     us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
     assert bs.last_status == 0
+
+
+def _batched_env(mg, probs, path):
+    import os
+    old = os.environ.get("MGFEM_BATCH_PATH")
+    os.environ["MGFEM_BATCH_PATH"] = path
+    try:
+        return mg.BatchedSolver([p.psi for p in probs], [p.N for p in probs])
+    finally:
+        if old is None:
+            del os.environ["MGFEM_BATCH_PATH"]
+        else:
+            os.environ["MGFEM_BATCH_PATH"] = old
+
+
+def test_tiled_batch_path_equals_single_mixed_solves():
+    """The tiled batch path runs each problem's steps with the kernels of the
+    single-problem mixed solve (all problems of a step in one launch), so
+    after fixed cycles every problem's iterate and max-norm history equal
+    that solver's bit for bit; and to the tolerance every problem converges
+    with the single solver's cycle count."""
+    mg = _gpu()
+    probs = W.batched_draws(count=12, seed=6, sizes=(64, 128, 256, 512))
+    bs = _batched_env(mg, probs, "tiled")
+    assert bs.tile == 0
+    us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=-1.0, max_cycles=3)
+    for p, u, h in zip(probs, us, hists):
+        s = mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
+        um, hm = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
+        assert np.array_equal(h, hm), (p.N, h, hm)
+        assert torch.equal(u, um), p.N
+    us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
+    assert bs.last_status == 0
+    for p, u, h in zip(probs, us, hists):
+        s = mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
+        um, hm = s.solve(p.f, p.g, tol=1e-10, max_cycles=80)
+        assert len(h) == len(hm) and torch.equal(u, um), p.N
+
+
+def test_persistent_batch_path_still_solves():
+    mg = _gpu()
+    probs = W.batched_draws(count=6, seed=7, sizes=(32, 64, 128))
+    bs = _batched_env(mg, probs, "persistent")
+    assert bs.tile in (32, 64, 128, 256)
+    us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
+    assert bs.last_status == 0
+    for p, u, h in zip(probs, us, hists):
+        d = oasm.assemble(p.psi, p.N)
+        ref = omg.solve(omg.build_hierarchy(d), d.rhs(p.f, p.g), tol=1e-14, max_cycles=100)
+        assert h[-1] <= 1e-10 * h[0]
+        assert rel_max(u.cpu().numpy(), ref.u) < 1e-8
