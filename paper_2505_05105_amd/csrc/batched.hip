@@ -250,6 +250,6 @@ int mgfem_solve_batched(mgfem_handle b, const double* const* f_dev, const double
   return MGFEM_OK;
 }
 
-int mgfem_batched_tile(mgfem_handle b) { return b ? b->batch.tx : -1; }
+int mgfem_batched_tile(mgfem_handle b) { return b && !b->members.empty() ? b->batch.tx : -1; }
 
 }  // extern "C"
