@@ -172,7 +172,8 @@ constexpr int kRedSlots = 8;
 // the coarse part leaves there, rows and columns in the order of idx.
 constexpr int kMaxMapNodes = 4096;  // larger first coarse levels keep the single-workgroup cycle
 struct CoarseMap {
-  int n = 0;             // active nodes of the first coarse level
+  int level = -1;        // the level whose coarse part the map stands for (-1: no map)
+  int n = 0;             // active nodes of that level
   int ld = 0;            // row stride (n rounded up to 16)
   int reps = 0;          // cycles of the coarse part the map stands for
   int* idx = nullptr;    // their grid indices on that level

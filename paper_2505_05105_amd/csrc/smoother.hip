@@ -1484,12 +1484,18 @@ const double* coarse_map<double>(const CoarseMap& M, bool reverse) { return M.f6
 template <>
 const float* coarse_map<float>(const CoarseMap& M, bool reverse) { return reverse ? nullptr : M.f32; }
 
+// the first level of a cycle's coarse part: where the coarse map applies,
+// else the single-workgroup part
+inline int coarse_level(const mgfem_ctx* c) {
+  return c->cplan.map.level >= 0 ? c->cplan.map.level : c->cplan.lc;
+}
+
 template <class T>
 void coarse_wg(mgfem_ctx* c, bool reverse, int reps) {
   CoarsePlan& P = c->cplan;
-  Level& Lc = c->lv[P.lc];
   const T* B = coarse_map<T>(P.map, reverse);
   if (B && reps == P.map.reps) {
+    Level& Lc = c->lv[P.map.level];
     const int n = P.map.n;
     hipLaunchKernelGGL(k_coarse_apply<T>, dim3(nblk(n, kMapWaves)), dim3(64 * kMapWaves),
                        P.map.ld * sizeof(T), c->s, B, P.map.ld, (const int*)P.map.idx, n,
@@ -1497,6 +1503,7 @@ void coarse_wg(mgfem_ctx* c, bool reverse, int reps) {
     Lc.cur = 0;
     return;
   }
+  Level& Lc = c->lv[P.lc];
   const CoarseArgs<T> a = coarse_args<T>(c, reverse, reps);
   const int lds = std::is_same<T, double>::value ? P.lds64 : P.lds32;
   hipLaunchKernelGGL(k_coarse<T>, dim3(1), dim3(kCoarseThreads), lds, c->s, a);
@@ -1506,7 +1513,8 @@ void coarse_wg(mgfem_ctx* c, bool reverse, int reps) {
 template <class T>
 void cycle_level(mgfem_ctx* c, int l, bool reverse, bool first_sweep_done = false) {
   const int nl = (int)c->lv.size();
-  if (c->cplan.lc >= 0 && l == c->cplan.lc) {
+  const int cl = coarse_level(c);
+  if (cl >= 0 && l == cl) {
     coarse_wg<T>(c, reverse, 1);
     return;
   }
@@ -1523,7 +1531,7 @@ void cycle_level(mgfem_ctx* c, int l, bool reverse, bool first_sweep_done = fals
   // solves the first coarse problem with coarse_cycles V-cycles from zero
   const bool two_grid = c->p.cycle == MGFEM_CYCLE_TWO_GRID && l == 0;
   const int visits = two_grid ? c->p.coarse_cycles : (c->p.cycle == MGFEM_CYCLE_W ? 2 : 1);
-  if (l + 1 == c->cplan.lc) coarse_wg<T>(c, reverse, visits);  // runs its visits itself
+  if (l + 1 == cl) coarse_wg<T>(c, reverse, visits);  // runs its visits itself
   else
     for (int g = 0; g < visits; ++g) cycle_level<T>(c, l + 1, reverse);
   if (reverse || post == 0) {
@@ -1826,6 +1834,249 @@ int build_tile_lists(mgfem_ctx* c) {
   return MGFEM_OK;
 }
 
+namespace {
+
+// column setup of an extended coarse map: b of column j is the unit vector
+// of the j0 + j-th active node (columns of nL values each)
+__global__ void k_unit_cols(double* __restrict__ b, int64_t nL, const int* __restrict__ idx, int j0, int J) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < J) b[j * nL + idx[j0 + j]] = 1.0;
+}
+
+// B[i ld + j0 + j] = x_j[idx[i]]: row i of the map, columns j0 ... j0 + J - 1
+__global__ void k_gather_cols(const double* __restrict__ x, int64_t nL, const int* __restrict__ idx, int n, int j0,
+                              int J, double* __restrict__ B, int ld) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && j < J) B[(int64_t)i * ld + j0 + j] = x[(int64_t)j * nL + idx[i]];
+}
+
+// BT = B^T for n x n matrices with row stride ld, through 32 x 32 LDS tiles
+__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ B, double* __restrict__ BT, int n,
+                                                   int ld) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int r = threadIdx.x / 32; r < 32; r += 8) {
+    const int i = by + r, j = bx + threadIdx.x % 32;
+    tile[r][threadIdx.x % 32] = (i < n && j < n) ? B[(int64_t)i * ld + j] : 0.0;
+  }
+  __syncthreads();
+  for (int r = threadIdx.x / 32; r < 32; r += 8) {
+    const int i = bx + r, j = by + threadIdx.x % 32;
+    if (i < n && j < n) BT[(int64_t)i * ld + j] = tile[threadIdx.x % 32][r];
+  }
+}
+
+__global__ void k_zero_f64(double* __restrict__ p, int64_t n) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0.0;
+}
+
+// the multi-problem kernels in float64, the columns of a map as the problems
+void col_launch(hipStream_t s, int kind, const void* tab, const int2* work, int nwork, int par, int prolong,
+                int lds) {
+  if (nwork <= 0) return;
+  const unsigned grid = 8u * (unsigned)((nwork + 7) / 8);
+  switch (kind) {
+    case kTeamSweep:
+      hipLaunchKernelGGL((k_sweep_multi<double, 16, 16, 512>), dim3(grid), dim3(512), 0, s,
+                         static_cast<const SweepEntry<double>*>(tab), work, nwork, par, 0, prolong);
+      break;
+    case kTeamCut:
+      hipLaunchKernelGGL(k_cut_multi<double>, dim3(grid), dim3(256), lds, s,
+                         static_cast<const CutEntry<double>*>(tab), work, nwork, par);
+      break;
+    case kTeamRR:
+      hipLaunchKernelGGL((k_resrestrict_multi<double, 16, 8, 512>), dim3(grid), dim3(512), 0, s,
+                         static_cast<const RrEntry<double>*>(tab), work, nwork, par, 0);
+      break;
+    case kTeamMap:
+      hipLaunchKernelGGL(k_coarse_apply_multi<double>, dim3(nwork), dim3(64 * kMapWaves), lds, s,
+                         static_cast<const MapEntry<double>*>(tab), work, nwork);
+      break;
+  }
+}
+
+template <class E>
+int upload_table(mgfem_ctx* c, const std::vector<E>& h, void** dev) {
+  MGFEM_HIP_TRY(hipMalloc(dev, h.size() * sizeof(E)));
+  MGFEM_HIP_TRY(hipMemcpyAsync(*dev, h.data(), h.size() * sizeof(E), hipMemcpyHostToDevice, c->s));
+  return MGFEM_OK;
+}
+
+}  // namespace
+
+// Extend the coarse map one level up, as long as that level is small: the
+// V-cycle from zero on level L (its smoothing, residual and restriction, the
+// coarse part through the map of level L + 1, prolongation and smoothing) is
+// again a fixed linear map of level L's right-hand side.  Its columns are the
+// results on the unit vectors, computed in batches of columns with the
+// multi-problem kernels in float64 (every column is a problem of its own with
+// its own vectors and the level's operators); the transposed cycle's map is
+// its transpose (the transposed cycle is the cycle's adjoint).  Not for
+// W-cycles (their coarse part repeats), nor up to level 1 of the two-grid
+// scheme (its first coarse problem takes coarse_cycles cycles).
+int extend_coarse_map(mgfem_ctx* c) {
+  CoarseMap& M = c->cplan.map;
+  const char* env = std::getenv("MGFEM_NO_MAP_EXTENSION");
+  if (env && env[0] && env[0] != '0') return MGFEM_OK;
+  while (M.level >= 2) {
+    const int C = M.level, L = C - 1;
+    if (!M.f64[0] || !M.f64[1] || M.reps != 1 || c->p.cycle == MGFEM_CYCLE_W || c->p.nu2 < 1) break;
+    if (c->p.cycle == MGFEM_CYCLE_TWO_GRID && L < 2) break;
+    Level& Ll = c->lv[L];
+    Level& Lc = c->lv[C];
+    if (Ll.empty() || Ll.n_active > kMaxMapNodes || sweep_shape(c, L) != kShapeSmall || Ll.N >= 1024) break;
+    const bool has_cut = c->p.eta > 0 && Ll.cut_off[4] > 0;
+    if (has_cut && !Ll.cp.ok) break;
+    // the active nodes of level L, ascending: rows and columns of the new map
+    std::vector<uint8_t> fl(Ll.n);
+    MGFEM_HIP_TRY(hipMemcpyAsync(fl.data(), Ll.flags, Ll.n, hipMemcpyDeviceToHost, c->s));
+    MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+    std::vector<int> idx;
+    for (int64_t k = 0; k < Ll.n; ++k)
+      if (fl[k] & kFlagActive) idx.push_back((int)k);
+    const int n = (int)idx.size();
+    if (n == 0 || n > kMaxMapNodes) break;
+    const int ld = (n + 15) / 16 * 16;
+    double* B = nullptr;
+    int* didx = nullptr;
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &B, (size_t)ld * n));
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &didx, n));
+    MGFEM_HIP_TRY(hipMemcpyAsync(didx, idx.data(), n * sizeof(int), hipMemcpyHostToDevice, c->s));
+    // vectors of a batch of J columns (freed below)
+    const int J = std::min(n, 512);
+    const int64_t nL = Ll.n, nC = Lc.n;
+    const int64_t ncL = std::max(1, Ll.cut_off[4]), ncC = std::max(1, Lc.cut_off[4]);
+    const int64_t total = 3 * J * nL + J * ncL + 3 * J * nC + J * ncC;
+    double* buf = nullptr;
+    MGFEM_HIP_TRY(hipMalloc(&buf, total * sizeof(double)));
+    double* XL = buf;               // buffer 0 of column j at XL + j nL, buffer 1 at XL + (J + j) nL
+    double* bL = XL + 2 * J * nL;
+    double* sL = bL + J * nL;
+    double* XC = sL + J * ncL;      // level C: buffer 0 (the map's output) and buffer 1
+    double* bC = XC + 2 * J * nC;
+    double* sC = bC + J * nC;
+    std::vector<SweepEntry<double>> ts(J);
+    std::vector<CutEntry<double>> tc(J);
+    std::vector<RrEntry<double>> tr(J);
+    std::vector<MapEntry<double>> tm(J);
+    for (int j = 0; j < J; ++j) {
+      SweepEntry<double>& e = ts[j];
+      e.a = sweep_args<double, 16, 16>(c, L, false, false, false);
+      e.a.b = bL + j * nL;
+      e.a.snap = sL + j * ncL;
+      e.a.sc = Lc.stride;
+      e.X[0] = XL + j * nL;
+      e.X[1] = XL + (J + j) * nL;
+      e.XC[0] = XC + j * nC;
+      e.XC[1] = XC + (J + j) * nC;
+      e.xc_fixed = 1;
+      if (has_cut) {
+        CutEntry<double>& u = tc[j];
+        u.a = cut_args<double>(c, L, false);
+        u.a.b = bL + j * nL;
+        u.a.snap = sL + j * ncL;
+        u.X[0] = e.X[0];
+        u.X[1] = e.X[1];
+      }
+      RrEntry<double>& r = tr[j];
+      r.a = rr_args<double, 16, 8>(c, L);
+      r.a.b = bL + j * nL;
+      r.a.bc = bC + j * nC;
+      r.a.snapc = sC + j * ncC;
+      r.X[0] = e.X[0];
+      r.X[1] = e.X[1];
+      r.XC[0] = XC + j * nC;
+      r.XC[1] = XC + (J + j) * nC;
+      r.xc_fixed = 1;
+      MapEntry<double>& m = tm[j];
+      m.B = M.f64[0];
+      m.ld = M.ld;
+      m.idx = M.idx;
+      m.n = M.n;
+      m.b = bC + j * nC;
+      m.x = XC + j * nC;
+    }
+    void *dts = nullptr, *dtc = nullptr, *dtr = nullptr, *dtm = nullptr;
+    int rc = upload_table(c, ts, &dts);
+    if (!rc) rc = upload_table(c, tc, &dtc);
+    if (!rc) rc = upload_table(c, tr, &dtr);
+    if (!rc) rc = upload_table(c, tm, &dtm);
+    // work lists, column by column (the first Jc columns are a prefix)
+    const int us = Ll.ntiles, uc = has_cut ? Ll.cp.ngroups : 0, ur = Lc.empty() ? 0 : Ll.rr_ntiles;
+    const int um = (M.n + kMapWaves - 1) / kMapWaves;
+    std::vector<int2> w;
+    for (int j = 0; j < J; ++j)
+      for (int q = 0; q < us; ++q) w.push_back(make_int2(j, q));
+    for (int j = 0; j < J; ++j)
+      for (int q = 0; q < uc; ++q) w.push_back(make_int2(j, q));
+    for (int j = 0; j < J; ++j)
+      for (int q = 0; q < ur; ++q) w.push_back(make_int2(j, q));
+    for (int j = 0; j < J; ++j)
+      for (int q = 0; q < um; ++q) w.push_back(make_int2(j, q));
+    int2* dw = nullptr;
+    if (!rc && hipMalloc(&dw, w.size() * sizeof(int2)) != hipSuccess) rc = MGFEM_ERR_OOM;
+    if (!rc && hipMemcpyAsync(dw, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice, c->s) != hipSuccess)
+      rc = MGFEM_ERR_HIP;
+    const int2* ws = dw;
+    const int2* wc = dw + (size_t)J * us;
+    const int2* wr = wc + (size_t)J * uc;
+    const int2* wm = wr + (size_t)J * ur;
+    const int cut_lds = Ll.cp.lds64, map_lds = M.ld * (int)sizeof(double);
+    for (int j0 = 0; j0 < n && !rc; j0 += J) {
+      const int Jc = std::min(J, n - j0);
+      hipLaunchKernelGGL(k_zero_f64, dim3(nblk(total, 256)), dim3(256), 0, c->s, buf, total);
+      hipLaunchKernelGGL(k_unit_cols, dim3(nblk(Jc, 256)), dim3(256), 0, c->s, bL, nL, (const int*)didx, j0, Jc);
+      int par = 0;
+      auto smooth_cols = [&](bool prolong) {
+        col_launch(c->s, kTeamSweep, dts, ws, Jc * us, par, prolong ? 1 : 0, 0);
+        par ^= 1;
+        if (has_cut) col_launch(c->s, kTeamCut, dtc, wc, Jc * uc, par, 0, cut_lds);
+      };
+      for (int st = 0; st < c->p.nu1; ++st) smooth_cols(false);
+      col_launch(c->s, kTeamRR, dtr, wr, Jc * ur, par, 0, 0);
+      col_launch(c->s, kTeamMap, dtm, wm, Jc * um, 0, 0, map_lds);
+      smooth_cols(true);  // x + P x_c, then the step
+      for (int st = 1; st < c->p.nu2; ++st) smooth_cols(false);
+      hipLaunchKernelGGL(k_gather_cols, dim3(nblk(Jc, 256), n), dim3(256), 0, c->s,
+                         (const double*)(XL + (par ? J * nL : 0)), nL, (const int*)didx, n, j0, Jc, B, ld);
+      if (hipGetLastError() != hipSuccess) rc = MGFEM_ERR_HIP;
+    }
+    if (hipStreamSynchronize(c->s) != hipSuccess && !rc) rc = MGFEM_ERR_HIP;
+    (void)hipFree(dw);
+    (void)hipFree(dts);
+    (void)hipFree(dtc);
+    (void)hipFree(dtr);
+    (void)hipFree(dtm);
+    (void)hipFree(buf);
+    if (rc) {
+      c->last_error = "coarse map extension to level " + std::to_string(L) + " failed";
+      return rc;
+    }
+    double* BT = nullptr;
+    MGFEM_HIP_TRY(ctx_alloc_t(c, &BT, (size_t)ld * n));
+    hipLaunchKernelGGL(k_transpose, dim3((n + 31) / 32, (n + 31) / 32), dim3(256), 0, c->s, (const double*)B, BT, n,
+                       ld);
+    float* B32 = nullptr;
+    if (c->p.precision == MGFEM_PREC_MIXED) {
+      MGFEM_HIP_TRY(ctx_alloc_t(c, &B32, (size_t)ld * n));
+      hipLaunchKernelGGL(k_f64_to_f32, dim3(nblk((int64_t)ld * n, 256)), dim3(256), 0, c->s, (const double*)B, B32,
+                         (int64_t)ld * n);
+    }
+    MGFEM_HIP_TRY(hipGetLastError());
+    MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+    M.level = L;
+    M.n = n;
+    M.ld = ld;
+    M.idx = didx;
+    M.f64[0] = B;
+    M.f64[1] = BT;
+    M.f32 = B32;
+  }
+  return MGFEM_OK;
+}
+
 int build_coarse_map(mgfem_ctx* c, bool forward_only) {
   CoarsePlan& P = c->cplan;
   CoarseMap& M = P.map;
@@ -1839,6 +2090,7 @@ int build_coarse_map(mgfem_ctx* c, bool forward_only) {
   // the first level of the coarse part)
   const bool two_grid = c->p.cycle == MGFEM_CYCLE_TWO_GRID && P.lc == 1;
   M.reps = two_grid ? c->p.coarse_cycles : (c->p.cycle == MGFEM_CYCLE_W ? 2 : 1);
+  M.level = P.lc;
   M.ld = (M.n + 15) / 16 * 16;
   const size_t cnt = (size_t)M.ld * M.n;
   for (int rev = 0; rev < (forward_only ? 1 : 2); ++rev) {
@@ -1857,6 +2109,7 @@ int build_coarse_map(mgfem_ctx* c, bool forward_only) {
     MGFEM_HIP_TRY(hipGetLastError());
   }
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
+  if (!forward_only) return extend_coarse_map(c);
   return MGFEM_OK;
 }
 
@@ -1875,6 +2128,8 @@ void set_kernel_attributes() {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cut<float>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cut_multi<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_cut_multi<double>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse<double>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, lds);

@@ -104,6 +104,22 @@ def _batched_env(mg, probs, path):
             os.environ["MGFEM_BATCH_PATH"] = old
 
 
+def _single_mixed(mg, p):
+    """The single-problem mixed solver with its coarse map on the first
+    single-workgroup level, as batch members have it (a single solver
+    otherwise extends the map to the levels above while they are small)."""
+    import os
+    old = os.environ.get("MGFEM_NO_MAP_EXTENSION")
+    os.environ["MGFEM_NO_MAP_EXTENSION"] = "1"
+    try:
+        return mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
+    finally:
+        if old is None:
+            del os.environ["MGFEM_NO_MAP_EXTENSION"]
+        else:
+            os.environ["MGFEM_NO_MAP_EXTENSION"] = old
+
+
 def test_tiled_batch_path_equals_single_mixed_solves():
     """The tiled batch path runs each problem's steps with the kernels of the
     single-problem mixed solve (all problems of a step in one launch), so
@@ -116,14 +132,14 @@ def test_tiled_batch_path_equals_single_mixed_solves():
     assert bs.tile == 0
     us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=-1.0, max_cycles=3)
     for p, u, h in zip(probs, us, hists):
-        s = mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
+        s = _single_mixed(mg, p)
         um, hm = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
         assert np.array_equal(h, hm), (p.N, h, hm)
         assert torch.equal(u, um), p.N
     us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
     assert bs.last_status == 0
     for p, u, h in zip(probs, us, hists):
-        s = mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
+        s = _single_mixed(mg, p)
         um, hm = s.solve(p.f, p.g, tol=1e-10, max_cycles=80)
         assert len(h) == len(hm) and torch.equal(u, um), p.N
 
