@@ -35,6 +35,9 @@ namespace mgfem {
 namespace {
 
 constexpr int kHalo = 4;
+// threads of a cut-group workgroup (a compile-time block size: reading blockDim
+// costs a load from the dispatch packet)
+constexpr int kCutThreads = 256;
 // threads of the single-workgroup coarse cycle: the levels it runs hold at
 // most a few thousand nodes, so few waves keep its many barriers cheap
 constexpr int kCoarseThreads = 256;
@@ -128,11 +131,11 @@ __device__ inline T gs_value(const T* __restrict__ A, int64_t n, int64_t k, bool
 //  norm:    before the first phase, the residual of the incoming iterate on
 //           the core is reduced into per-tile partials (max |r|, sum r^2).
 // final reduction of (max, sum) pairs in a fixed order
-__global__ void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out, double* host_out,
+__global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out, double* host_out,
                                double* seq) {
   __shared__ double smx[256], ssm[256];
   double mx = 0.0, sm = 0.0;
-  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+  for (int q = threadIdx.x; q < nb; q += 256) {
     mx = nanmax2(mx, part[2 * q]);
     sm += part[2 * q + 1];
   }
@@ -483,7 +486,7 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
   uint8_t wo[KW];
 #pragma unroll
   for (int u = 0; u < KW; ++u) {
-    const int t = threadIdx.x + u * blockDim.x;
+    const int t = threadIdx.x + u * kCutThreads;
     wo[u] = 0;
     wk[u] = 0;
     if (t < cl_cnt) {
@@ -491,8 +494,8 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
       wk[u] = stage(t);
     }
   }
-  for (int t = threadIdx.x + KW * blockDim.x; t < cl_cnt; t += blockDim.x) stage(t);
-  for (int t = threadIdx.x; t <= ext_cnt; t += blockDim.x) {
+  for (int t = threadIdx.x + KW * kCutThreads; t < cl_cnt; t += kCutThreads) stage(t);
+  for (int t = threadIdx.x; t <= ext_cnt; t += kCutThreads) {
     T v = T(0);
     if (t < ext_cnt) {
       const int src = a.ext_src[ext_off + t];
@@ -530,8 +533,8 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
       for (int e = 0; e < 8; ++e) acc -= rcf[c][e] * nb[e];
       vals[rt[c]] = acc * rinv[c];
     }
-    const int lo = gi[4 + c] + blockDim.x, hi = gi[5 + c];
-    for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+    const int lo = gi[4 + c] + kCutThreads, hi = gi[5 + c];
+    for (int t = lo + threadIdx.x; t < hi; t += kCutThreads) {
       const Refs8 rr = srefs[t];
       T nb[8];
 #pragma unroll
@@ -560,13 +563,13 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
   }
 #pragma unroll
   for (int u = 0; u < KW; ++u)
-    if (wo[u]) a.x[wk[u]] = vals[threadIdx.x + u * blockDim.x];
-  for (int t = threadIdx.x + KW * blockDim.x; t < cl_cnt; t += blockDim.x)
+    if (wo[u]) a.x[wk[u]] = vals[threadIdx.x + u * kCutThreads];
+  for (int t = threadIdx.x + KW * kCutThreads; t < cl_cnt; t += kCutThreads)
     if (a.cl_own[cl_off + t]) a.x[a.cl_node[cl_off + t]] = vals[t];
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_cut(CutArgs<T> a) {
+__global__ __launch_bounds__(kCutThreads) void k_cut(CutArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   cut_group<T>(a, blockIdx.x, smem);
 }
@@ -578,7 +581,7 @@ struct CutEntry {
 };
 
 template <class T>
-__global__ __launch_bounds__(256) void k_cut_multi(const CutEntry<T>* tab, const int2* work, int nwork, int par) {
+__global__ __launch_bounds__(kCutThreads) void k_cut_multi(const CutEntry<T>* tab, const int2* work, int nwork, int par) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int i = xcd_item((nwork + 7) >> 3);
   if (i >= nwork) return;
@@ -660,17 +663,15 @@ __device__ void rr_tile(const ResArgs<T>& a, const int t) {
       const int gi = ux0 + q % UW, gj = uy0 + q / UW;
       ru[it] = (q < UW * UH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.x[gi + (int64_t)gj * a.s] : T(0);
     }
+    // flags and b together (b of an inactive node is loaded and never used),
+    // so that no load waits for another
 #pragma unroll
     for (int it = 0; it < NR; ++it) {
       const int q = tid + BS * it;
       const int gi = fx0 + q % RW, gj = fy0 + q / RW;
-      rf[it] = (q < RW * RH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N) ? a.fl[gi + (int64_t)gj * a.s] : 0;
-    }
-#pragma unroll
-    for (int it = 0; it < NR; ++it) {
-      const int q = tid + BS * it;
-      const int gi = fx0 + q % RW, gj = fy0 + q / RW;
-      rb[it] = (rf[it] & kFlagActive) ? a.b[gi + (int64_t)gj * a.s] : T(0);
+      const bool in = q < RW * RH && gi >= 0 && gj >= 0 && gi <= a.N && gj <= a.N;
+      rf[it] = in ? a.fl[gi + (int64_t)gj * a.s] : 0;
+      rb[it] = in ? a.b[gi + (int64_t)gj * a.s] : T(0);
     }
 #pragma unroll
     for (int it = 0; it < NU; ++it) {
@@ -1164,36 +1165,61 @@ struct MapEntry {
 
 // rows kMapWaves blk ... kMapWaves (blk + 1) - 1 of x = B b (sb: ld values of LDS)
 template <class T>
-__device__ void map_rows(const T* __restrict__ B, int ld, const int* __restrict__ idx, int n,
+__device__ __forceinline__ void map_rows(const T* __restrict__ B, int ld, const int* __restrict__ idx, int n,
                          const T* __restrict__ b, T* __restrict__ x, const int blk, T* sb) {
   using V = typename Vec16<T>::type;
   constexpr int G = 16 / (int)sizeof(T);  // values per 16-byte load
-  constexpr int U = 8;                    // loads in flight per lane
+  constexpr int U = 4;                    // loads per lane and round; two rounds in flight
   constexpr int CH = U * 64 * G;          // values of a row per round
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = blk * kMapWaves + wave;
   const T* row = B + (int64_t)(r < n ? r : 0) * ld;
-  V v[U];
-  auto load = [&](int base) {
+  // two rounds of the row in flight at a time (double-buffered registers)
+  V v0[U], v1[U];
+  auto load = [&](V* v, int base) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int col = base + (u * 64 + lane) * G;
       v[u] = col < ld ? *reinterpret_cast<const V*>(row + col) : V{};
     }
   };
-  load(0);
-  for (int j = threadIdx.x; j < ld; j += blockDim.x) sb[j] = j < n ? b[idx[j]] : T(0);
-  __syncthreads();
   T acc = T(0);
-  for (int base = 0;;) {
+  auto dot = [&](const V* v, int base) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int col = base + (u * 64 + lane) * G;
       if (col < ld) acc += Vec16<T>::dot(v[u], sb + col);
     }
-    base += CH;
-    if (base >= ld) break;
-    load(base);
+  };
+  load(v0, 0);
+  load(v1, CH);
+  // b gathered into LDS, GC values per thread at a time with all their loads
+  // in flight: the indices, then the values (n >= 1)
+  {
+    constexpr int NT = 64 * kMapWaves, GC = 8;
+    for (int j0 = 0; j0 < ld; j0 += GC * NT) {
+      int ii[GC];
+#pragma unroll
+      for (int u = 0; u < GC; ++u) {
+        const int j = j0 + (int)threadIdx.x + u * NT;
+        ii[u] = idx[j < n ? j : n - 1];
+      }
+      T bv[GC];
+#pragma unroll
+      for (int u = 0; u < GC; ++u) bv[u] = b[ii[u]];
+#pragma unroll
+      for (int u = 0; u < GC; ++u) {
+        const int j = j0 + (int)threadIdx.x + u * NT;
+        if (j < ld) sb[j] = j < n ? bv[u] : T(0);
+      }
+    }
+  }
+  __syncthreads();
+  for (int base = 0; base < ld; base += 2 * CH) {
+    dot(v0, base);
+    if (base + 2 * CH < ld) load(v0, base + 2 * CH);
+    if (base + CH < ld) dot(v1, base + CH);
+    if (base + 3 * CH < ld) load(v1, base + 3 * CH);
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0 && r < n) x[idx[r]] = acc;
@@ -1367,7 +1393,7 @@ void cut_sweeps(mgfem_ctx* c, int l, bool reverse) {
   if (L.cp.ok) {
     const CutArgs<T> a = cut_args<T>(c, l, reverse);
     const size_t lds = std::is_same<T, double>::value ? L.cp.lds64 : L.cp.lds32;
-    hipLaunchKernelGGL(k_cut<T>, dim3(L.cp.ngroups), dim3(256), lds, c->s, a);
+    hipLaunchKernelGGL(k_cut<T>, dim3(L.cp.ngroups), dim3(kCutThreads), lds, c->s, a);
     return;
   }
   for (int e = 0; e < eta; ++e)
@@ -1655,7 +1681,7 @@ void team_launch(hipStream_t s, int kind, const void* tab, const int2* work, int
                          static_cast<const SweepEntry<float>*>(tab), work, nwork, par, parc, prolong);
       break;
     case kTeamCut:
-      hipLaunchKernelGGL(k_cut_multi<float>, dim3(grid), dim3(256), lds, s, static_cast<const CutEntry<float>*>(tab),
+      hipLaunchKernelGGL(k_cut_multi<float>, dim3(grid), dim3(kCutThreads), lds, s, static_cast<const CutEntry<float>*>(tab),
                          work, nwork, par);
       break;
     case kTeamRR:
@@ -1883,7 +1909,7 @@ void col_launch(hipStream_t s, int kind, const void* tab, const int2* work, int 
                          static_cast<const SweepEntry<double>*>(tab), work, nwork, par, 0, prolong);
       break;
     case kTeamCut:
-      hipLaunchKernelGGL(k_cut_multi<double>, dim3(grid), dim3(256), lds, s,
+      hipLaunchKernelGGL(k_cut_multi<double>, dim3(grid), dim3(kCutThreads), lds, s,
                          static_cast<const CutEntry<double>*>(tab), work, nwork, par);
       break;
     case kTeamRR:
