@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-hbm", action="store_true", help="skip the N=16384 leg (working set above the MALL)")
     ap.add_argument("--hbm-N", type=int, default=16384)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--inner-cycles", type=int, default=3,
+                    help="mixed precision (single and batched): float32 cycles per float64 defect-correction step")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched, adjoint and further-form legs")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--copy-probe", action="store_true",
@@ -118,9 +120,10 @@ def cpu_baseline(prob, N, solves):
 
 def bench_batched(args, mg, W, torch, dev):
     """Batched form: `args.batch` seeded random ellipses, N drawn from
-    {64, 128, 256, 512}, f ~ U[-1, 1], g = 0, one persistent launch per solve
-    (float32 cycles with float64 refinement), against the plain float64
-    single-problem solver run over the same problems one after another."""
+    {64, 128, 256, 512}, f ~ U[-1, 1], g = 0, float32 cycles with float64
+    refinement (`args.inner_cycles` float32 cycles per refinement step), the
+    path the autotuner picks, against the plain float64 single-problem solver
+    run over the same problems one after another."""
     import numpy as np
     probs = W.batched_draws(count=args.batch, seed=0)
     psis = [torch.tensor(p.psi, device=dev) for p in probs]
@@ -128,7 +131,7 @@ def bench_batched(args, mg, W, torch, dev):
     gs = [torch.tensor(p.g, device=dev) for p in probs]
     Ns = [p.N for p in probs]
     t0 = time.perf_counter()
-    bs = mg.BatchedSolver(psis, Ns)
+    bs = mg.BatchedSolver(psis, Ns, inner_cycles=args.inner_cycles)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     outs = [torch.empty((n + 1) ** 2, dtype=torch.float64, device=dev) for n in Ns]
@@ -165,7 +168,7 @@ def bench_batched(args, mg, W, torch, dev):
     return {"value": dof / (ms * 1e-3), "unit": "DOF/s", "ms_per_step": ms, "problems": len(probs),
             "active_dof": dof, "N_counts": {str(n): Ns.count(n) for n in sorted(set(Ns))},
             "cycles_max": max(cycles), "cycles_mean": float(np.mean(cycles)),
-            "worst_final_rel_residual": worst, "autotuned_tile": tile, "setup_s": setup_s,
+            "worst_final_rel_residual": worst, "autotuned_tile": tile, "inner_cycles": args.inner_cycles, "setup_s": setup_s,
             "fp64_sequential_ms": ms_seq, "speedup_vs_fp64_sequential": ms_seq / ms,
             "dtype": "f32 cycles / f64 refinement"}
 
@@ -367,7 +370,7 @@ def bench_hbm(args, mg, W, torch, dev):
     # the mixed-precision solve of the same problem (float32 cycles, float64
     # outer step): at this size the bytes of the large levels dominate
     psi = W.flower_mms_device(N, dev)[0]
-    sm = mg.Solver(psi, N, precision=mg.PREC_MIXED)
+    sm = mg.Solver(psi, N, precision=mg.PREC_MIXED, inner_cycles=args.inner_cycles)
     del psi
     um = torch.empty_like(u)
     _, hm = sm.solve(f, g, tol=args.tol, max_cycles=100, out=um)
@@ -378,6 +381,7 @@ def bench_hbm(args, mg, W, torch, dev):
     torch.cuda.synchronize()
     msm = (time.perf_counter() - t0) * 1e3 / steps
     roof["mixed"] = {"ms_per_solve": msm, "dof_per_s": dof / (msm * 1e-3), "cycles": len(hm) - 1,
+                     "inner_cycles": args.inner_cycles,
                      "speedup_vs_fp64": ms / msm, "final_rel_residual": float(hm[-1] / hm[0]),
                      "rel_err_vs_fp64_gpu": float((um - u).abs().max() / u.abs().max())}
     log(f"[bench] hbm leg N={N} mixed: {msm:.2f} ms/solve, {len(hm) - 1} cycles, {ms / msm:.2f}x the float64 solve")
@@ -400,7 +404,8 @@ def bench_ellipse_mixed(args, mg, W, torch, dev, with_oracle):
     rec = {}
     sols = {}
     for name, prec in (("fp64", mg.PREC_FP64), ("mixed", mg.PREC_MIXED)):
-        s = mg.Solver(psi, N, precision=prec)
+        kw = {"inner_cycles": args.inner_cycles} if prec == mg.PREC_MIXED else {}
+        s = mg.Solver(psi, N, precision=prec, **kw)
         u = torch.empty((N + 1) ** 2, dtype=torch.float64, device=dev)
         for _ in range(args.warmup):
             _, h = s.solve(f, g, tol=args.tol, max_cycles=100, out=u)
@@ -530,7 +535,7 @@ def main():
 
     u_mixed = None
     if not args.no_mixed:
-        smx = mg.Solver(psi, N, precision=mg.PREC_MIXED)
+        smx = mg.Solver(psi, N, precision=mg.PREC_MIXED, inner_cycles=args.inner_cycles)
         um = torch.empty_like(u)
         for _ in range(args.warmup):
             hm = run(smx, um)
@@ -546,7 +551,8 @@ def main():
         # the float32 finest sweep timed the same way
         roof32 = sweep_roofline(smx, lambda: run(smx, um), 1, args.steps, args.profile_repeat, None)
         out["mixed"] = {"value": dof / (msm * 1e-3), "unit": "DOF/s", "ms_per_step": msm,
-                        "cycles": len(hm) - 1, "dtype": "f32 cycles / f64 outer",
+                        "cycles": len(hm) - 1, "inner_cycles": args.inner_cycles,
+                        "float_cycles": (len(hm) - 1) * args.inner_cycles, "dtype": "f32 cycles / f64 outer",
                         "rel_err_vs_fp64_gpu": err, "final_rel_residual": float(hm[-1] / hm[0]),
                         "speedup_vs_fp64": ms / msm, "roofline": roof32}
         log(f"[bench] mixed: {msm:.3f} ms/solve, {len(hm) - 1} cycles, err vs fp64 {err:.2e}")

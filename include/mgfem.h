@@ -113,6 +113,10 @@ typedef struct {
   double x_lo, y_lo, x_hi, y_hi; /* square box; default [-1, 1]^2 */
   int32_t coarse_cycles; /* MGFEM_CYCLE_TWO_GRID: V-cycles of the coarse solve (1..1000); default 40 */
   int32_t coarse_op;     /* enum mgfem_coarse_op, default MGFEM_COARSE_GALERKIN */
+  int32_t inner_cycles;  /* MGFEM_PREC_MIXED: float32 cycles per float64 defect-correction
+                            step (1..16; the first starts from zero, the others continue
+                            from it); default 1.  The residual history and max_cycles
+                            count the defect-correction steps */
 } mgfem_params;
 
 typedef struct {

@@ -38,7 +38,7 @@ class Params(C.Structure):
         ("snap_alpha", C.c_double), ("nu1", C.c_int32), ("nu2", C.c_int32), ("eta", C.c_int32),
         ("coarsest_n", C.c_int32), ("precision", C.c_int32), ("cycle", C.c_int32),
         ("x_lo", C.c_double), ("y_lo", C.c_double), ("x_hi", C.c_double), ("y_hi", C.c_double),
-        ("coarse_cycles", C.c_int32), ("coarse_op", C.c_int32),
+        ("coarse_cycles", C.c_int32), ("coarse_op", C.c_int32), ("inner_cycles", C.c_int32),
     ]
 
 

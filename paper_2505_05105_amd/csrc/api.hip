@@ -36,6 +36,8 @@ int check_params(const mgfem_params& p, int N, std::string& why) {
     return why = "nu1/nu2/eta", 1;
   if (p.coarsest_n < 1 || p.coarsest_n > 16) return why = "coarsest_n must be in [1, 16]", 1;
   if (p.precision != MGFEM_PREC_FP64 && p.precision != MGFEM_PREC_MIXED) return why = "precision", 1;
+  if (p.precision == MGFEM_PREC_MIXED && (p.inner_cycles < 1 || p.inner_cycles > 16))
+    return why = "inner_cycles must be 1..16", 1;
   if (p.cycle != MGFEM_CYCLE_V && p.cycle != MGFEM_CYCLE_W && p.cycle != MGFEM_CYCLE_TWO_GRID)
     return why = "cycle", 1;
   if (p.cycle == MGFEM_CYCLE_TWO_GRID && (p.coarse_cycles < 1 || p.coarse_cycles > 1000))
@@ -197,6 +199,7 @@ int mgfem_default_params(mgfem_params* p) {
   p->cycle = MGFEM_CYCLE_V;
   p->coarse_cycles = 40;
   p->coarse_op = MGFEM_COARSE_GALERKIN;
+  p->inner_cycles = 1;
   p->x_lo = -1.0;
   p->y_lo = -1.0;
   p->x_hi = 1.0;
@@ -447,9 +450,9 @@ int read_norm(mgfem_ctx* c, double& mx, double& l2, double* raw_sum = nullptr, d
 //  float64 forward: the rest of the cycle (its first sweep ran in the previous
 //    iteration), then the first sweep of the next cycle with the fused norm of
 //    its incoming iterate (speculative: discarded when the loop stops);
-//  mixed: a float cycle from zero on the float residual of the previous
-//    step, then one fused pass u += e, r = F - A u (float64), its float copy,
-//    the next zero start iterate and the norm;
+//  mixed: inner_cycles float cycles on the float residual of the previous
+//    step (the first from zero), then one fused pass u += e, r = F - A u
+//    (float64), its float copy, the next zero start iterate and the norm;
 //  adjoint: a transposed cycle, then the residual norm.
 struct IterKind {
   bool mixed, reverse, first_done;
@@ -462,7 +465,7 @@ void enqueue_iteration(mgfem_ctx* c, const IterKind& k) {
     CycleOpts o;
     o.fp32 = true;
     o.reverse = k.reverse;
-    run_cycle(c, o);
+    for (int q = 0; q < c->p.inner_cycles; ++q) run_cycle(c, o);
     const int ce = L0.cur;
     launch_outer(c, L0.X[c->u_cur], L0.X32[ce], L0.X[1 - c->u_cur], L0.b32, L0.X32[1 - ce]);
     c->u_cur = 1 - c->u_cur;

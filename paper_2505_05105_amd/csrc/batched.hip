@@ -36,8 +36,8 @@ std::string tune_key(const std::vector<int>& Ns, const mgfem_params& p) {
   long long sum = 0;
   for (int n : Ns) sum += (long long)(n + 1) * (n + 1);
   char buf[256];
-  std::snprintf(buf, sizeof buf, "%s|paths=2|count=%zu|nodes=%lld|eta=%d|nu=%d,%d", arch.c_str(), Ns.size(), sum,
-                p.eta, p.nu1, p.nu2);
+  std::snprintf(buf, sizeof buf, "%s|paths=2|count=%zu|nodes=%lld|eta=%d|nu=%d,%d|inner=%d", arch.c_str(), Ns.size(),
+                sum, p.eta, p.nu1, p.nu2, p.inner_cycles);
   return buf;
 }
 

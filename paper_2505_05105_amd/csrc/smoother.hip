@@ -2282,6 +2282,7 @@ struct BatchArgs {
   int* ncyc;
   double tol;
   int max_cycles, nu1, nu2, eta, tx;
+  int inner;  // float32 cycles per float64 step
   unsigned int* queue;
 };
 
@@ -2423,7 +2424,7 @@ __device__ void solve_one(const BatchArgs& a, int p, unsigned char* base, int* s
   int grow = 0;
   // rel_tol <= 0: exactly max_cycles cycles
   while (m < a.max_cycles && !(a.tol > 0.0 && mx <= a.tol * fnorm) && mx == mx) {
-    // inner float32 cycle on A e = r from e = 0
+    // inner float32 cycles on A e = r, the first from e = 0
     const BLevel& L0 = P.lev[0];
     wg_for_sublattice(P.i0, P.i1, P.j0, P.j1, -1, -1, tx, [&](int i, int j) {
       const int64_t k = i + (int64_t)j * P.s0;
@@ -2431,14 +2432,16 @@ __device__ void solve_one(const BatchArgs& a, int p, unsigned char* base, int* s
       L0.x[k] = 0.f;
     });
     __syncthreads();
-    for (int l = 0; l < P.nlev; ++l) {
-      for (int s = 0; s < a.nu1; ++s) b_smooth(P.lev[l], a.eta, tx);
-      b_restrict(P.lev[l], P.lev[l + 1], tx);
-    }
-    coarse_body<float>(P.ca, base, sdesc);
-    for (int l = P.nlev - 1; l >= 0; --l) {
-      b_prolong(P.lev[l], P.lev[l + 1], tx);
-      for (int s = 0; s < a.nu2; ++s) b_smooth(P.lev[l], a.eta, tx);
+    for (int ic = 0; ic < a.inner; ++ic) {
+      for (int l = 0; l < P.nlev; ++l) {
+        for (int s = 0; s < a.nu1; ++s) b_smooth(P.lev[l], a.eta, tx);
+        b_restrict(P.lev[l], P.lev[l + 1], tx);
+      }
+      coarse_body<float>(P.ca, base, sdesc);
+      for (int l = P.nlev - 1; l >= 0; --l) {
+        b_prolong(P.lev[l], P.lev[l + 1], tx);
+        for (int s = 0; s < a.nu2; ++s) b_smooth(P.lev[l], a.eta, tx);
+      }
     }
     // float64 update and residual
     wg_for_sublattice(P.i0, P.i1, P.j0, P.j1, -1, -1, tx, [&](int i, int j) {
@@ -2565,6 +2568,7 @@ float launch_batched(mgfem_ctx* b, BatchDevice& d, int count, double tol, int ma
   a.nu2 = b->p.nu2;
   a.eta = b->p.eta;
   a.tx = tx;
+  a.inner = b->p.inner_cycles;
   a.queue = d.queue;
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);

@@ -246,7 +246,7 @@ int team_solve(mgfem_ctx* b, const double* const* f, const double* const* g, dou
   active.swap(next);
   while (!active.empty() && m < max_cycles) {
     if (changed && (rc = team_lists(b, T, active, false))) return rc;
-    team_level(b, T, 0, par);
+    for (int q = 0; q < b->p.inner_cycles; ++q) team_level(b, T, 0, par);
     const int ce = par[0];
     launch_l0(b, T, kTeamOuter, upar, ce);
     upar ^= 1;

@@ -91,12 +91,12 @@ def test_single_problem_calls_reject_a_batched_handle():
     assert bs.last_status == 0
 
 
-def _batched_env(mg, probs, path):
+def _batched_env(mg, probs, path, **params):
     import os
     old = os.environ.get("MGFEM_BATCH_PATH")
     os.environ["MGFEM_BATCH_PATH"] = path
     try:
-        return mg.BatchedSolver([p.psi for p in probs], [p.N for p in probs])
+        return mg.BatchedSolver([p.psi for p in probs], [p.N for p in probs], **params)
     finally:
         if old is None:
             del os.environ["MGFEM_BATCH_PATH"]
@@ -104,7 +104,7 @@ def _batched_env(mg, probs, path):
             os.environ["MGFEM_BATCH_PATH"] = old
 
 
-def _single_mixed(mg, p):
+def _single_mixed(mg, p, **params):
     """The single-problem mixed solver with its coarse map on the first
     single-workgroup level, as batch members have it (a single solver
     otherwise extends the map to the levels above while they are small)."""
@@ -112,7 +112,7 @@ def _single_mixed(mg, p):
     old = os.environ.get("MGFEM_NO_MAP_EXTENSION")
     os.environ["MGFEM_NO_MAP_EXTENSION"] = "1"
     try:
-        return mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED)
+        return mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED, **params)
     finally:
         if old is None:
             del os.environ["MGFEM_NO_MAP_EXTENSION"]
@@ -120,26 +120,28 @@ def _single_mixed(mg, p):
             os.environ["MGFEM_NO_MAP_EXTENSION"] = old
 
 
-def test_tiled_batch_path_equals_single_mixed_solves():
+@pytest.mark.parametrize("inner", [1, 2])
+def test_tiled_batch_path_equals_single_mixed_solves(inner):
     """The tiled batch path runs each problem's steps with the kernels of the
     single-problem mixed solve (all problems of a step in one launch), so
     after fixed cycles every problem's iterate and max-norm history equal
-    that solver's bit for bit; and to the tolerance every problem converges
-    with the single solver's cycle count."""
+    that solver's bit for bit, also with several float32 cycles per float64
+    step; and to the tolerance every problem converges with the single
+    solver's cycle count."""
     mg = _gpu()
     probs = W.batched_draws(count=12, seed=6, sizes=(64, 128, 256, 512))
-    bs = _batched_env(mg, probs, "tiled")
+    bs = _batched_env(mg, probs, "tiled", inner_cycles=inner)
     assert bs.tile == 0
     us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=-1.0, max_cycles=3)
     for p, u, h in zip(probs, us, hists):
-        s = _single_mixed(mg, p)
+        s = _single_mixed(mg, p, inner_cycles=inner)
         um, hm = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
         assert np.array_equal(h, hm), (p.N, h, hm)
         assert torch.equal(u, um), p.N
     us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
     assert bs.last_status == 0
     for p, u, h in zip(probs, us, hists):
-        s = _single_mixed(mg, p)
+        s = _single_mixed(mg, p, inner_cycles=inner)
         um, hm = s.solve(p.f, p.g, tol=1e-10, max_cycles=80)
         assert len(h) == len(hm) and torch.equal(u, um), p.N
 

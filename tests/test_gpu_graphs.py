@@ -175,13 +175,15 @@ def test_list_smoother_without_group_plans():
     assert slm.last_status == 0 and torch.abs(um - ug).max() <= 1e-8 * torch.abs(ug).max()
 
 
-def test_profiled_mixed_replay_times_the_float_sweep():
+@pytest.mark.parametrize("inner", [1, 3])
+def test_profiled_mixed_replay_times_the_float_sweep(inner):
     """Class 1: the float32 finest sweeps of the mixed cycles, three per
-    outer iteration; the profiled solve equals the unprofiled one."""
+    float32 cycle and `inner` cycles per outer iteration; the profiled solve
+    equals the unprofiled one."""
     mg = _gpu()
     N = 2048
     p = W.flower_mms(N)
-    s = mg.Solver(p.psi, N, precision=mg.PREC_MIXED)
+    s = mg.Solver(p.psi, N, precision=mg.PREC_MIXED, inner_cycles=inner)
     u0, h0 = s.solve(p.f, p.g, tol=1e-10)
     s.profile(True)
     u1, h1 = s.solve(p.f, p.g, tol=1e-10)
@@ -189,7 +191,7 @@ def test_profiled_mixed_replay_times_the_float_sweep():
     assert s.profile_read(0)["launches"] == 0
     s.profile(False)
     assert np.array_equal(h0, h1) and torch.equal(u0, u1)
-    assert prof["launches"] == 3 * (len(h1) - 1)
+    assert prof["launches"] == 3 * inner * (len(h1) - 1)
     assert prof["total_ms"] > 0 and prof["alg_bytes"] > 0
 
 

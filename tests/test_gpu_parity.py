@@ -183,16 +183,19 @@ def test_mixed_precision_reaches_fp64_tolerance():
     F = d.rhs(p.f, p.g)
     ref = omg.solve(H, F, tol=1e-14, max_cycles=80)
     s64 = mg.Solver(p.psi, 256)
-    s = mg.Solver(p.psi, 256, precision=mg.PREC_MIXED)
-    for tol in (1e-10, 1e-12):
-        u64, _ = s64.solve(p.f, p.g, tol=tol, max_cycles=80)
-        err64 = rel_max(u64.cpu().numpy(), ref.u)
-        u, hist = s.solve(p.f, p.g, tol=tol, max_cycles=80)
-        assert s.last_status == 0
-        assert hist[-1] <= tol * np.abs(F).max()
-        err = rel_max(u.cpu().numpy(), ref.u)
-        # the error is set by the residual tolerance, as for the FP64 solve
-        assert err < 10 * err64 + 1e-13, (tol, err, err64)
+    for inner in (1, 2, 3):
+        s = mg.Solver(p.psi, 256, precision=mg.PREC_MIXED, inner_cycles=inner)
+        for tol in (1e-10, 1e-12):
+            u64, _ = s64.solve(p.f, p.g, tol=tol, max_cycles=80)
+            err64 = rel_max(u64.cpu().numpy(), ref.u)
+            u, hist = s.solve(p.f, p.g, tol=tol, max_cycles=80)
+            assert s.last_status == 0
+            assert hist[-1] <= tol * np.abs(F).max()
+            err = rel_max(u.cpu().numpy(), ref.u)
+            # the error is set by the residual tolerance, as for the FP64 solve
+            assert err < 10 * err64 + 1e-13, (inner, tol, err, err64)
+    with pytest.raises(mg.MgfemError):
+        mg.Solver(p.psi, 256, precision=mg.PREC_MIXED, inner_cycles=0)
 
 
 @pytest.mark.parametrize("k", [2, 5])
