@@ -115,7 +115,7 @@ typedef struct {
   int32_t coarse_op;     /* enum mgfem_coarse_op, default MGFEM_COARSE_GALERKIN */
   int32_t inner_cycles;  /* MGFEM_PREC_MIXED: float32 cycles per float64 defect-correction
                             step (1..16; the first starts from zero, the others continue
-                            from it); default 1.  The residual history and max_cycles
+                            from it); default 3.  The residual history and max_cycles
                             count the defect-correction steps */
 } mgfem_params;
 

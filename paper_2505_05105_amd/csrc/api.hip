@@ -199,7 +199,7 @@ int mgfem_default_params(mgfem_params* p) {
   p->cycle = MGFEM_CYCLE_V;
   p->coarse_cycles = 40;
   p->coarse_op = MGFEM_COARSE_GALERKIN;
-  p->inner_cycles = 1;
+  p->inner_cycles = 3;
   p->x_lo = -1.0;
   p->y_lo = -1.0;
   p->x_hi = 1.0;

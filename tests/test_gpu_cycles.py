@@ -189,7 +189,7 @@ def test_rediscretised_adjoint_and_mixed_precision():
     ref = oadj.adjoint_solve(H, r, tol=-1.0, max_cycles=3)
     assert rel_max(lam.cpu().numpy(), ref.u) < 1e-10
     F = d.rhs(p.f, p.g)
-    sm = mg.Solver(p.psi, N, coarse_op=mg.COARSE_REDISCRETISED, precision=mg.PREC_MIXED)
+    sm = mg.Solver(p.psi, N, coarse_op=mg.COARSE_REDISCRETISED, precision=mg.PREC_MIXED, inner_cycles=1)
     u, hist = sm.solve(p.f, p.g, tol=1e-10, max_cycles=60)
     assert sm.last_status == 0 and hist[-1] <= 1e-10 * np.abs(F).max()
     direct = omg.solve(H, F, tol=1e-14, max_cycles=100).u

@@ -156,7 +156,7 @@ def test_list_smoother_without_group_plans():
     try:
         sl = _solver(mg, p, N, True)
         sle = _solver(mg, p, N, False)
-        slm = _solver(mg, p, N, True, precision=1)
+        slm = _solver(mg, p, N, True, precision=1, inner_cycles=1)
     finally:
         if old is None:
             del os.environ["MGFEM_NO_CUT_GROUPS"]
@@ -208,7 +208,7 @@ def _solver_env(mg, p, N, env, **kw):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("kw", [{}, {"cycle": 2}, {"cycle": 3}, {"precision": 1}],
+@pytest.mark.parametrize("kw", [{}, {"cycle": 2}, {"cycle": 3}, {"precision": 1, "inner_cycles": 1}],
                          ids=["V", "W", "two_grid", "mixed"])
 def test_coarse_map_equals_the_coarse_cycle(kw):
     """The coarse part applied as its precomputed dense map (the default)
