@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-solves", type=int, default=3, help="oracle solves timed (median reported)")
+    ap.add_argument("--no-cpu-scaling", action="store_true",
+                    help="skip the oracle at N = 1024, 2048 and the all-threads solve")
     ap.add_argument("--profile-repeat", type=int, default=10,
                     help="each timed sweep launch repeated back to back between its events")
     ap.add_argument("--no-hbm", action="store_true", help="skip the N=16384 leg (working set above the MALL)")
@@ -116,6 +118,39 @@ def cpu_baseline(prob, N, solves):
         "hist": [float(x) for x in res.hist], "u": res.u,
         "cpu": _cpu_name(), "nproc": os.cpu_count(),
     }
+
+
+def cpu_scaling(W, solves):
+    """The oracle at the smaller flower sizes (N = 1024, 2048) on one
+    thread, and at N = 4096 with the thread pools unlimited (one solve):
+    median solve times, set-up apart."""
+    import numpy as np
+    from oracle import assembly as oasm
+    from oracle import multigrid as omg
+    out = {"by_size": []}
+    with _one_thread():
+        for n in (1024, 2048):
+            prob = W.flower_mms(n)
+            d = oasm.assemble(prob.psi, n)
+            H = omg.build_hierarchy(d)
+            times = []
+            for _ in range(solves):
+                ts = time.perf_counter()
+                res = omg.solve(H, d.rhs(prob.f, prob.g), tol=1e-10, max_cycles=60)
+                times.append(time.perf_counter() - ts)
+            med = float(np.median(times))
+            dof = int(d.active.sum())
+            out["by_size"].append({"N": n, "dof": dof, "cycles": int(res.cycles), "median_s": med,
+                                   "dof_per_s": dof / med, "cores": 1})
+    prob = W.flower_mms(4096)
+    d = oasm.assemble(prob.psi, 4096)
+    H = omg.build_hierarchy(d)
+    ts = time.perf_counter()
+    res = omg.solve(H, d.rhs(prob.f, prob.g), tol=1e-10, max_cycles=60)
+    t = time.perf_counter() - ts
+    out["all_threads_n4096"] = {"solve_s": t, "dof_per_s": int(d.active.sum()) / t, "cores": os.cpu_count(),
+                                "note": "thread pools unlimited; scipy's sparse products stay single-threaded"}
+    return out
 
 
 def bench_batched(args, mg, W, torch, dev):
@@ -533,6 +568,15 @@ def main():
         "levels": [dict(N=s64.level_n(l), **s64.level_counts(l)) for l in range(info["n_levels"])],
     }
 
+    # the converged discrete solution (the same float64 solver run far past the
+    # tolerance): what the errors of both forms at the 1e-10 residual are
+    # measured against, beside their distance to the oracle at that tolerance
+    ut = torch.empty_like(u)
+    _, ht = s64.solve(f, g, tol=1e-15, max_cycles=80, out=ut, raise_on_fail=False)
+    uts = float(ut.abs().max())
+    out["fp64_rel_err_vs_converged"] = float((u - ut).abs().max()) / uts
+    out["converged_reference"] = {"cycles": len(ht) - 1, "final_rel_residual": float(ht[-1] / ht[0])}
+
     u_mixed = None
     if not args.no_mixed:
         smx = mg.Solver(psi, N, precision=mg.PREC_MIXED, inner_cycles=args.inner_cycles)
@@ -554,14 +598,15 @@ def main():
                         "cycles": len(hm) - 1, "inner_cycles": args.inner_cycles,
                         "float_cycles": (len(hm) - 1) * args.inner_cycles, "dtype": "f32 cycles / f64 outer",
                         "rel_err_vs_fp64_gpu": err, "final_rel_residual": float(hm[-1] / hm[0]),
-                        "speedup_vs_fp64": ms / msm, "roofline": roof32}
+                        "speedup_vs_fp64": ms / msm, "roofline": roof32,
+                        "rel_err_vs_converged": float((um - ut).abs().max()) / uts}
         log(f"[bench] mixed: {msm:.3f} ms/solve, {len(hm) - 1} cycles, err vs fp64 {err:.2e}")
         smx.close()
 
     u_fp64 = u.cpu().numpy()
     s64.close()
     if not args.no_hbm:
-        del f, g, psi, u
+        del f, g, psi, u, ut
         torch.cuda.empty_cache()
         out["roofline_hbm"] = bench_hbm(args, mg, W, torch, dev)
 
@@ -597,6 +642,9 @@ def main():
         k = min(len(hc), len(hist))
         out["cpu_baseline"]["hist_rel_diff_vs_gpu"] = float(
             np.max(np.abs(hc[:k] - hist[:k]) / np.abs(hist[:k])))
+        if args.domain == "flower" and N == 4096 and not args.no_cpu_scaling:
+            log("[bench] cpu baseline at N = 1024, 2048 and on every thread")
+            out["cpu_baseline"].update(cpu_scaling(W, args.cpu_solves))
     print(json.dumps(out), flush=True)
 
 
