@@ -187,7 +187,8 @@ int mgfem_setup_mixed_bc(const double* psi_dev, const double* chi_dev, int32_t N
  *                  ||F - A u_m||_inf (entry 0 for the start), section 3.1.
  *  n_cycles      : host, receives the number of cycles run (may be NULL).
  * In mixed precision one cycle is one float64 outer defect-correction step
- * around one float32 cycle.  Returns OK, NOT_CONVERGED, DIVERGED or an error.
+ * around params.inner_cycles float32 cycles (the first from zero).  Returns
+ * OK, NOT_CONVERGED, DIVERGED or an error.
  */
 int mgfem_solve(mgfem_handle h, const double* f_dev, const double* g_dev, double rel_tol,
                 int32_t max_cycles, uint32_t flags, double* u_dev, double* res_hist_host,
@@ -346,9 +347,10 @@ const char* mgfem_last_error(mgfem_handle h);
  * coarse-map rows, ...) of every problem still iterating, with the kernels
  * and results of the single-problem mixed solve; or one persistent launch
  * whose workgroups take whole problems from a queue, with one of four
- * footprint widths.  Parameters are shared by all problems; the whole
- * boundary is Dirichlet.  MGFEM_BATCH_PATH=tiled or =persistent at set-up
- * fixes the choice.
+ * footprint widths.  Parameters are shared by all problems (both paths run
+ * params.inner_cycles float32 cycles per float64 step, as mgfem_solve in
+ * mixed precision); the whole boundary is Dirichlet.  MGFEM_BATCH_PATH=tiled
+ * or =persistent at set-up fixes the choice.
  *  psi_dev[i] : device (N[i]+1)^2 float64.  N[i] as in mgfem_setup.
  */
 int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32_t* N,

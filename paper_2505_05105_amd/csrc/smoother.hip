@@ -24,7 +24,17 @@
 //  k_resrestrict  residual r = b - A x on a fine tile and its restriction
 //               b_c = R r (weights 1, 1/2, 1/4) in one pass; zeroes x_c.
 //  k_prolong    x += P x_c (bilinear) at active fine nodes.
-//  k_coarse     the V-cycle of all remaining coarse levels in one workgroup.
+//  k_coarse_apply  the coarse part of the cycle (from the first level with at
+//               most a few thousand unknowns down) as one dense matrix-vector
+//               product; the matrix is computed at set-up.
+//  k_coarse     the cycle of the coarsest levels in one workgroup, the levels
+//               in LDS: builds the dense map at set-up (one unit right-hand
+//               side per workgroup) and runs where no map is kept.
+//  k_*_multi    the same tile, group and row bodies for many problems in one
+//               launch (batched solves): a table of per-problem arguments and
+//               a list of (problem, unit) work items.
+//  k_batched    the persistent alternative for batched solves: one workgroup
+//               per problem, drawn from an atomic queue.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
