@@ -416,7 +416,7 @@ def bench_hbm(args, mg, W, torch, dev):
     torch.cuda.synchronize()
     msm = (time.perf_counter() - t0) * 1e3 / steps
     roof["mixed"] = {"ms_per_solve": msm, "dof_per_s": dof / (msm * 1e-3), "cycles": len(hm) - 1,
-                     "inner_cycles": args.inner_cycles,
+                     "inner_cycles": args.inner_cycles, "step_cycles": [int(k) for k in sm.step_cycles()],
                      "speedup_vs_fp64": ms / msm, "final_rel_residual": float(hm[-1] / hm[0]),
                      "rel_err_vs_fp64_gpu": float((um - u).abs().max() / u.abs().max())}
     log(f"[bench] hbm leg N={N} mixed: {msm:.2f} ms/solve, {len(hm) - 1} cycles, {ms / msm:.2f}x the float64 solve")
@@ -455,6 +455,8 @@ def bench_ellipse_mixed(args, mg, W, torch, dev, with_oracle):
         dof = s.info()["n_active"]
         rec[name] = {"ms_per_step": ms, "value": dof / (ms * 1e-3), "unit": "DOF/s", "cycles": len(h) - 1,
                      "final_rel_residual": float(h[-1] / h[0])}
+        if prec == mg.PREC_MIXED:
+            rec[name]["step_cycles"] = [int(k) for k in s.step_cycles()]
         sols[name] = u
         if prec == mg.PREC_FP64:
             # the converged discrete solution the errors of both forms are measured against
@@ -599,13 +601,15 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         msm = (t1 - t0) * 1e3 / args.steps
+        step_cycles = [int(k) for k in smx.step_cycles()]
         err = float((um - u).abs().max() / u.abs().max())
         u_mixed = um.cpu().numpy()
         # the float32 finest sweep timed the same way
         roof32 = sweep_roofline(smx, lambda: run(smx, um), 1, args.steps, args.profile_repeat, None)
         out["mixed"] = {"value": dof / (msm * 1e-3), "unit": "DOF/s", "ms_per_step": msm,
                         "cycles": len(hm) - 1, "inner_cycles": args.inner_cycles,
-                        "float_cycles": (len(hm) - 1) * args.inner_cycles, "dtype": "f32 cycles / f64 outer",
+                        "float_cycles": sum(step_cycles), "step_cycles": step_cycles,
+                        "dtype": "f32 cycles / f64 outer",
                         "rel_err_vs_fp64_gpu": err, "final_rel_residual": float(hm[-1] / hm[0]),
                         "speedup_vs_fp64": ms / msm, "roofline": roof32,
                         "rel_err_vs_converged": float((um - ut).abs().max()) / uts}

@@ -115,8 +115,12 @@ typedef struct {
   int32_t coarse_op;     /* enum mgfem_coarse_op, default MGFEM_COARSE_GALERKIN */
   int32_t inner_cycles;  /* MGFEM_PREC_MIXED: float32 cycles per float64 defect-correction
                             step (1..16; the first starts from zero, the others continue
-                            from it); default 3.  The residual history and max_cycles
-                            count the defect-correction steps */
+                            from it); default 3.  With rel_tol > 0 a step runs fewer
+                            where the factor per float32 cycle of an earlier step says
+                            fewer reach the tolerance (environment MGFEM_FIXED_INNER=1
+                            keeps the full count; mgfem_step_cycles reports the counts).
+                            The residual history and max_cycles count the
+                            defect-correction steps */
 } mgfem_params;
 
 typedef struct {
@@ -187,7 +191,7 @@ int mgfem_setup_mixed_bc(const double* psi_dev, const double* chi_dev, int32_t N
  *                  ||F - A u_m||_inf (entry 0 for the start), section 3.1.
  *  n_cycles      : host, receives the number of cycles run (may be NULL).
  * In mixed precision one cycle is one float64 outer defect-correction step
- * around params.inner_cycles float32 cycles (the first from zero).  Returns
+ * around up to params.inner_cycles float32 cycles (the first from zero).  Returns
  * OK, NOT_CONVERGED, DIVERGED or an error.
  */
 int mgfem_solve(mgfem_handle h, const double* f_dev, const double* g_dev, double rel_tol,
@@ -300,6 +304,19 @@ int mgfem_smooth(mgfem_handle h, int32_t level, double* x_dev, const double* b_d
  * Returns INVALID_ARG for a NULL handle or a negative capacity.
  */
 int mgfem_residual_l2(mgfem_handle h, double* l2_hist_host, int32_t capacity, int32_t* count);
+
+/*
+ * The number of V-cycles each iteration of the last mgfem_solve,
+ * mgfem_solve_mixed_bc or mgfem_adjoint on this handle ran, m = 1..cycles:
+ * 1 for float64 iterations; for MGFEM_PRECISION_MIXED the float32 cycles of
+ * each float64 step (params.inner_cycles, fewer where the residual history
+ * shows that fewer reach the tolerance).
+ *  cycles_host : host, room for `capacity` int32 (may be NULL when capacity
+ *                is 0); receives the first min(capacity, count).
+ *  count       : host, receives the number of iterations (may be NULL).
+ * Returns INVALID_ARG for a NULL handle or a negative capacity.
+ */
+int mgfem_step_cycles(mgfem_handle h, int32_t* cycles_host, int32_t capacity, int32_t* count);
 
 /* Per-level row counts: active rows, rows whose stencil is read from the
  * stored planes (the others are the interior Q1 stencil), extra-smoothing

@@ -89,6 +89,17 @@ class Solver:
                                                     cnt.value, C.byref(cnt)), self.handle)
         return out
 
+    def step_cycles(self):
+        """V-cycles run by each iteration of the last solve or adjoint (mixed
+        precision: the float32 cycles of each float64 step)."""
+        cnt = C.c_int32(0)
+        _lib.check(_lib.lib().mgfem_step_cycles(self.handle, None, 0, C.byref(cnt)), self.handle)
+        out = np.zeros(cnt.value, dtype=np.int32)
+        if cnt.value:
+            _lib.check(_lib.lib().mgfem_step_cycles(self.handle, out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                    cnt.value, C.byref(cnt)), self.handle)
+        return out
+
     def level_n(self, level):
         return _lib.lib().mgfem_level_n(self.handle, level)
 

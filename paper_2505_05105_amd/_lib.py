@@ -28,7 +28,7 @@ EXPORTED = (
     "mgfem_status_string", "mgfem_last_error", "mgfem_setup_batched", "mgfem_solve_batched",
     "mgfem_level_counts", "mgfem_profile", "mgfem_profile_read", "mgfem_batched_tile",
     "mgfem_setup_mixed_bc", "mgfem_solve_mixed_bc", "mgfem_adjoint_neumann", "mgfem_residual_l2",
-    "mgfem_misfit_noalloc",
+    "mgfem_misfit_noalloc", "mgfem_step_cycles",
 )
 
 
@@ -92,6 +92,7 @@ def lib():
         "mgfem_profile_read": (C.c_int, [P, I32, C.POINTER(C.c_int64), DP, DP]),
         "mgfem_batched_tile": (C.c_int, [P]),
         "mgfem_residual_l2": (C.c_int, [P, DP, I32, C.POINTER(I32)]),
+        "mgfem_step_cycles": (C.c_int, [P, C.POINTER(I32), I32, C.POINTER(I32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

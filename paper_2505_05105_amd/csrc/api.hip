@@ -456,6 +456,7 @@ int read_norm(mgfem_ctx* c, double& mx, double& l2, double* raw_sum = nullptr, d
 //  adjoint: a transposed cycle, then the residual norm.
 struct IterKind {
   bool mixed, reverse, first_done;
+  int inner;  // mixed: float32 cycles of this step
 };
 void enqueue_iteration(mgfem_ctx* c, const IterKind& k) {
   Level& L0 = c->lv[0];
@@ -465,7 +466,7 @@ void enqueue_iteration(mgfem_ctx* c, const IterKind& k) {
     CycleOpts o;
     o.fp32 = true;
     o.reverse = k.reverse;
-    for (int q = 0; q < c->p.inner_cycles; ++q) run_cycle(c, o);
+    for (int q = 0; q < k.inner; ++q) run_cycle(c, o);
     const int ce = L0.cur;
     launch_outer(c, L0.X[c->u_cur], L0.X32[ce], L0.X[1 - c->u_cur], L0.b32, L0.X32[1 - ce]);
     c->u_cur = 1 - c->u_cur;
@@ -497,7 +498,7 @@ void set_loop_state(mgfem_ctx* c, const std::vector<int>& st) {
 }
 
 std::vector<int> graph_key(mgfem_ctx* c, const IterKind& k) {
-  std::vector<int> key{k.mixed, k.reverse, k.first_done, c->prof.on ? 1 : 0};
+  std::vector<int> key{k.mixed, k.reverse, k.first_done, c->prof.on ? 1 : 0, k.inner};
   for (int v : loop_state(c)) key.push_back(v);
   return key;
 }
@@ -585,8 +586,16 @@ int run_iteration(mgfem_ctx* c, const IterKind& k, const GraphEntry** used) {
 int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cycles, bool reverse,
             bool mixed, bool warm, double bnorm, double* hist, int* ncyc) {
   Level& L0 = c->lv[0];
+  // the loop reads its own history (step lengths, queueing), so it keeps one
+  // when the caller asks for none
+  std::vector<double> own_hist;
+  if (!hist) {
+    own_hist.resize((size_t)std::max(0, max_cycles) + 1);
+    hist = own_hist.data();
+  }
   double r0, l2, l2F = c->f_l2;
   c->l2_hist.clear();
+  c->step_cycles.clear();
   L0.X[0] = c->x0;
   L0.b = const_cast<double*>(b);
   L0.cur = 0;
@@ -639,10 +648,58 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   Pending pend[2];
   int queued = 0;
   double* result = c->x0;  // the iterate returned when the loop stops
+  // The queue-ahead test with i norms read: the last factor applied once more
+  // leaves the residual 4x above the target, so the iteration after the one
+  // in flight will most likely be needed.
+  auto would_queue = [&](int i) -> bool {
+    const double rho = i > 0 ? hist[i] / std::max(hist[i - 1], 1e-300) : 1.0;
+    return rel_tol <= 0.0 || hist[i] * rho > 4.0 * rel_tol * bnorm;
+  };
+  // Mixed precision: step j runs inner_cycles float32 cycles, or fewer where
+  // the residuals say fewer reach the tolerance (so the last step does not
+  // over-solve).  The count depends on the history alone, never on when the
+  // loop reads it (a profiled solve reads every norm before it launches, an
+  // unprofiled one queues ahead), so both run the same steps:
+  //  - a step that would be queued ahead starts from the residual predicted
+  //    after the step in flight;
+  //  - any other step is launched after the norm of the step before it has
+  //    been read and starts from that norm.
+  // The factor per float32 cycle is that of the last step whose two norms
+  // are known; the count is the number of such factors that bring the
+  // starting residual to the target, rounded up.
+  const int K = mixed ? c->p.inner_cycles : 1;
+  std::vector<int> step_inner;  // float32 cycles of each launched step
+  const char* fi_env = std::getenv("MGFEM_FIXED_INNER");
+  const bool adapt = mixed && K > 1 && rel_tol > 0.0 && !(fi_env && fi_env[0] && fi_env[0] != '0');
+  auto inner_for = [&](int j) -> int {  // step j = 1, 2, ...
+    const int i = j - 2;                // norms read when step j would be queued ahead
+    if (!adapt || i < 0) return K;
+    int k0;          // the step whose factor is used: norms k0 - 1 and k0
+    double r_start;  // the residual step j starts from
+    if (would_queue(i)) {
+      if (i < 1) return K;
+      k0 = i;
+      r_start = -1.0;  // predicted below, after the step in flight
+    } else {
+      if (m != j - 1) return K;  // not reached: such a step is launched after that read
+      k0 = j - 1;
+      r_start = hist[j - 1];
+    }
+    const double r1 = hist[k0], r0 = hist[k0 - 1];
+    const int kc = step_inner[k0 - 1];
+    if (!(r1 > 0.0) || !(r0 > r1) || kc < 1) return K;
+    const double rho = std::pow(r1 / r0, 1.0 / kc);
+    if (r_start < 0.0) r_start = hist[i] * std::pow(rho, step_inner[i]);
+    const double need = std::log(rel_tol * bnorm / r_start) / std::log(rho);
+    if (!std::isfinite(need)) return K;
+    return std::max(1, std::min(K, (int)std::ceil(need)));
+  };
   auto launch = [&](Pending& out) -> int {
     const GraphEntry* g = nullptr;
-    const int e = run_iteration(c, IterKind{mixed, reverse, first_done}, &g);
+    const int inner = inner_for((int)step_inner.size() + 1);
+    const int e = run_iteration(c, IterKind{mixed, reverse, first_done, inner}, &g);
     if (e) return e;
+    step_inner.push_back(inner);
     first_done = fused;
     out.seq = c->red_seq;
     out.g = g;
@@ -656,15 +713,11 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
     queued = 1;
   }
   while (queued > 0) {
-    // queue the next iteration now when it will most likely be needed: the
-    // last factor applied once more leaves the residual 4x above the target
-    if (ahead && queued == 1 && m + 1 < max_cycles) {
-      const double rho = (m > 0 && hist) ? hist[m] / std::max(hist[m - 1], 1e-300) : 1.0;
-      if (rel_tol <= 0.0 || prev * rho > 4.0 * rel_tol * bnorm) {
-        rc = launch(pend[1]);
-        if (rc) return rc;
-        queued = 2;
-      }
+    // queue the next iteration now when it will most likely be needed
+    if (ahead && queued == 1 && m + 1 < max_cycles && would_queue(m)) {
+      rc = launch(pend[1]);
+      if (rc) return rc;
+      queued = 2;
     }
     double rm;
     rc = read_norm(c, rm, l2, nullptr, pend[0].seq);
@@ -699,6 +752,7 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   }
   // an iteration still queued is discarded: it never writes `result` (the
   // export below is ordered after it on the stream)
+  c->step_cycles.assign(step_inner.begin(), step_inner.begin() + std::min<size_t>(m, step_inner.size()));
   launch_export(c, x, result);
   MGFEM_HIP_TRY(hipGetLastError());
   MGFEM_HIP_TRY(hipStreamSynchronize(c->s));
@@ -973,6 +1027,14 @@ int mgfem_residual_l2(mgfem_handle c, double* l2_hist_host, int32_t capacity, in
   const int n = std::min(capacity, (int)c->l2_hist.size());
   for (int m = 0; m < n; ++m) l2_hist_host[m] = c->l2_hist[m];
   if (count) *count = (int32_t)c->l2_hist.size();
+  return MGFEM_OK;
+}
+
+int mgfem_step_cycles(mgfem_handle c, int32_t* cycles_host, int32_t capacity, int32_t* count) {
+  if (!c || capacity < 0 || (capacity > 0 && !cycles_host)) return MGFEM_ERR_INVALID_ARG;
+  const int n = std::min(capacity, (int)c->step_cycles.size());
+  for (int m = 0; m < n; ++m) cycles_host[m] = c->step_cycles[m];
+  if (count) *count = (int32_t)c->step_cycles.size();
   return MGFEM_OK;
 }
 

@@ -336,6 +336,7 @@ struct mgfem_ctx {
   int u_cur = 0;                    // mixed precision: which level-0 float64 buffer holds u
   double f_l2 = 0.0;                // ||F||_2 of the right-hand side the last solve assembled
   std::vector<double> l2_hist;      // ||F - A u_m||_2 of the last solve or adjoint, m = 0..cycles
+  std::vector<int> step_cycles;     // V-cycles run by each iteration of the last solve or adjoint
   std::string last_error;
   int device = 0;                   // device that was current at set-up
   bool batched_member = false;

@@ -104,20 +104,33 @@ def _batched_env(mg, probs, path, **params):
             os.environ["MGFEM_BATCH_PATH"] = old
 
 
+class _env:
+    """Set environment variables for the duration of a with-block."""
+
+    def __init__(self, **kv):
+        self.kv, self.old = kv, {}
+
+    def __enter__(self):
+        import os
+        for k, v in self.kv.items():
+            self.old[k] = os.environ.get(k)
+            os.environ[k] = v
+
+    def __exit__(self, *exc):
+        import os
+        for k, v in self.old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+
+
 def _single_mixed(mg, p, **params):
     """The single-problem mixed solver with its coarse map on the first
     single-workgroup level, as batch members have it (a single solver
     otherwise extends the map to the levels above while they are small)."""
-    import os
-    old = os.environ.get("MGFEM_NO_MAP_EXTENSION")
-    os.environ["MGFEM_NO_MAP_EXTENSION"] = "1"
-    try:
+    with _env(MGFEM_NO_MAP_EXTENSION="1"):
         return mg.Solver(p.psi, p.N, precision=mg.PREC_MIXED, **params)
-    finally:
-        if old is None:
-            del os.environ["MGFEM_NO_MAP_EXTENSION"]
-        else:
-            os.environ["MGFEM_NO_MAP_EXTENSION"] = old
 
 
 @pytest.mark.parametrize("inner", [1, 2])
@@ -142,7 +155,10 @@ def test_tiled_batch_path_equals_single_mixed_solves(inner):
     assert bs.last_status == 0
     for p, u, h in zip(probs, us, hists):
         s = _single_mixed(mg, p, inner_cycles=inner)
-        um, hm = s.solve(p.f, p.g, tol=1e-10, max_cycles=80)
+        # the batch runs every step with inner_cycles float32 cycles; the
+        # single solver would shorten its last step
+        with _env(MGFEM_FIXED_INNER="1"):
+            um, hm = s.solve(p.f, p.g, tol=1e-10, max_cycles=80)
         assert len(h) == len(hm) and torch.equal(u, um), p.N
 
 

@@ -111,10 +111,12 @@ def test_profiled_replay_times_the_sweep():
 def test_mixed_loop_queued_iteration_is_discarded():
     """The mixed loop queues its next iteration before reading the norm it
     waits for; when that norm meets the tolerance the queued iteration is
-    dropped.  Loose tolerances (the first cycles' factors improve on the
-    factor the queueing predicts with) must return exactly the iterate and
-    history of a run with the same number of cycles and no tolerance, the
-    profiled loop (which never queues ahead) must agree bit for bit, and the
+    dropped.  With every step at the full float32 cycle count, loose
+    tolerances (the first cycles' factors improve on the factor the queueing
+    predicts with) must return exactly the iterate and history of a run with
+    the same number of cycles and no tolerance; with the last steps
+    shortened from the residual history, the profiled loop (which never
+    queues ahead) must agree bit for bit with the queueing one; and the
     solver must be unchanged for the next solve."""
     mg = _gpu()
     N = 256
@@ -123,19 +125,54 @@ def test_mixed_loop_queued_iteration_is_discarded():
     fresh = _solver(mg, p, N, True, precision=1)
     ref_u, ref_h = fresh.solve(p.f, p.g, tol=1e-10)
     for tol in (0.3, 0.1, 3e-2, 1e-3, 1e-6):
+        os.environ["MGFEM_FIXED_INNER"] = "1"
+        try:
+            u, h = s.solve(p.f, p.g, tol=tol)
+            assert list(s.step_cycles()) == [3] * (len(h) - 1)
+            k = len(h) - 1
+            assert s.last_status == 0 and h[-1] <= tol * h[0] < h[-2]  # u = 0: h[0] is the norm of F
+            uf, hf = s.solve(p.f, p.g, tol=-1.0, max_cycles=k)
+            torch.cuda.synchronize()
+            assert np.array_equal(h, hf), tol
+            assert torch.equal(u, uf), tol
+        finally:
+            del os.environ["MGFEM_FIXED_INNER"]
         u, h = s.solve(p.f, p.g, tol=tol)
-        k = len(h) - 1
-        assert s.last_status == 0 and h[-1] <= tol * h[0] < h[-2]  # u = 0: h[0] is the norm of F
-        uf, hf = s.solve(p.f, p.g, tol=-1.0, max_cycles=k)
-        torch.cuda.synchronize()
-        assert np.array_equal(h, hf), tol
-        assert torch.equal(u, uf), tol
+        sc = s.step_cycles()
+        assert s.last_status == 0 and h[-1] <= tol * h[0] and len(sc) == len(h) - 1
         s.profile(True)
         up, hp = s.solve(p.f, p.g, tol=tol)
         s.profile(False)
         assert np.array_equal(h, hp) and torch.equal(u, up), tol
+        assert np.array_equal(sc, s.step_cycles()), tol
     u, h = s.solve(p.f, p.g, tol=1e-10)
     assert np.array_equal(h, ref_h) and torch.equal(u, ref_u)
+
+
+def test_mixed_steps_shortened_from_the_history():
+    """Step lengths: the full count while the target is far, fewer only for
+    the last steps, never more in total than with every step at the full
+    count, and the tolerance still met."""
+    mg = _gpu()
+    for name, N in (("flower", 1024), ("ellipse", 1024)):
+        p = W.flower_mms(N) if name == "flower" else W.ellipse_mms(N)
+        s = _solver(mg, p, N, True, precision=1)
+        u, h = s.solve(p.f, p.g, tol=1e-10)
+        sc = list(s.step_cycles())
+        assert s.last_status == 0 and h[-1] <= 1e-10 * h[0] and len(sc) == len(h) - 1
+        assert all(1 <= k <= 3 for k in sc) and sc[0] == 3
+        # shortened steps come only at the end
+        first_short = next((i for i, k in enumerate(sc) if k < 3), len(sc))
+        assert len(sc) - first_short <= 2, sc
+        os.environ["MGFEM_FIXED_INNER"] = "1"
+        try:
+            uf, hf = s.solve(p.f, p.g, tol=1e-10)
+            scf = list(s.step_cycles())
+        finally:
+            del os.environ["MGFEM_FIXED_INNER"]
+        assert scf == [3] * (len(hf) - 1)
+        assert sum(sc) <= sum(scf), (name, sc, scf)
+        print(f"{name} N={N}: float32 cycles per step {sc} (fixed: {scf})")
 
 
 def test_list_smoother_without_group_plans():
@@ -191,7 +228,9 @@ def test_profiled_mixed_replay_times_the_float_sweep(inner):
     assert s.profile_read(0)["launches"] == 0
     s.profile(False)
     assert np.array_equal(h0, h1) and torch.equal(u0, u1)
-    assert prof["launches"] == 3 * inner * (len(h1) - 1)
+    sc = s.step_cycles()
+    assert len(sc) == len(h1) - 1 and all(1 <= k <= inner for k in sc)
+    assert prof["launches"] == 3 * int(sc.sum())
     assert prof["total_ms"] > 0 and prof["alg_bytes"] > 0
 
 
