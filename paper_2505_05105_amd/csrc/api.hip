@@ -659,38 +659,23 @@ int iterate(mgfem_ctx* c, double* x, const double* b, double rel_tol, int max_cy
   // the residuals say fewer reach the tolerance (so the last step does not
   // over-solve).  The count depends on the history alone, never on when the
   // loop reads it (a profiled solve reads every norm before it launches, an
-  // unprofiled one queues ahead), so both run the same steps:
-  //  - a step that would be queued ahead starts from the residual predicted
-  //    after the step in flight;
-  //  - any other step is launched after the norm of the step before it has
-  //    been read and starts from that norm.
-  // The factor per float32 cycle is that of the last step whose two norms
-  // are known; the count is the number of such factors that bring the
-  // starting residual to the target, rounded up.
+  // unprofiled one queues ahead), so both run the same steps: a step that
+  // would be queued ahead runs the full count; any other is launched after
+  // the norm of the step before it has been read and runs as many cycles as
+  // the factor per float32 cycle of that step needs to bring that norm to the
+  // target, rounded up.  The first step's factor is not used: its first
+  // cycles converge much faster than the later ones.
   const int K = mixed ? c->p.inner_cycles : 1;
   std::vector<int> step_inner;  // float32 cycles of each launched step
   const char* fi_env = std::getenv("MGFEM_FIXED_INNER");
   const bool adapt = mixed && K > 1 && rel_tol > 0.0 && !(fi_env && fi_env[0] && fi_env[0] != '0');
   auto inner_for = [&](int j) -> int {  // step j = 1, 2, ...
-    const int i = j - 2;                // norms read when step j would be queued ahead
-    if (!adapt || i < 0) return K;
-    int k0;          // the step whose factor is used: norms k0 - 1 and k0
-    double r_start;  // the residual step j starts from
-    if (would_queue(i)) {
-      if (i < 1) return K;
-      k0 = i;
-      r_start = -1.0;  // predicted below, after the step in flight
-    } else {
-      if (m != j - 1) return K;  // not reached: such a step is launched after that read
-      k0 = j - 1;
-      r_start = hist[j - 1];
-    }
-    const double r1 = hist[k0], r0 = hist[k0 - 1];
-    const int kc = step_inner[k0 - 1];
-    if (!(r1 > 0.0) || !(r0 > r1) || kc < 1) return K;
-    const double rho = std::pow(r1 / r0, 1.0 / kc);
-    if (r_start < 0.0) r_start = hist[i] * std::pow(rho, step_inner[i]);
-    const double need = std::log(rel_tol * bnorm / r_start) / std::log(rho);
+    if (!adapt || j < 3 || would_queue(j - 2) || m != j - 1) return K;
+    const double r = hist[j - 1], rp = hist[j - 2];
+    const int kp = step_inner[j - 2];
+    if (!(r > 0.0) || !(rp > r) || kp < 1) return K;
+    const double rho = std::pow(r / rp, 1.0 / kp);
+    const double need = std::log(rel_tol * bnorm / r) / std::log(rho);
     if (!std::isfinite(need)) return K;
     return std::max(1, std::min(K, (int)std::ceil(need)));
   };
