@@ -465,6 +465,12 @@ template <class T>
 __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem) {
   const int* gi = a.g_info + 9 * g;
   const int cl_off = gi[0], cl_cnt = gi[1], ext_off = gi[2], ext_cnt = gi[3];
+  // the colour ranges in registers: a value read from global memory after a
+  // workgroup barrier is loaded again (the barrier orders global memory too),
+  // and that load would sit in every colour phase
+  int cr[5];
+#pragma unroll
+  for (int e = 0; e < 5; ++e) cr[e] = gi[4 + e];
   const CutLds lay = cut_lds_layout(cl_cnt, ext_cnt, (int)sizeof(T));
   T* vals = reinterpret_cast<T*>(smem + lay.vals);
   T* sb = reinterpret_cast<T*>(smem + lay.b);
@@ -521,8 +527,8 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
   T rb[4], rinv[4], rcf[4][8];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int t = gi[4 + c] + threadIdx.x;
-    rt[c] = t < gi[5 + c] ? t : -1;
+    const int t = cr[c] + threadIdx.x;
+    rt[c] = t < cr[c + 1] ? t : -1;
     const int tt = rt[c] >= 0 ? t : 0;
     rrf[c] = srefs[tt];
     rb[c] = sb[tt];
@@ -543,7 +549,7 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
       for (int e = 0; e < 8; ++e) acc -= rcf[c][e] * nb[e];
       vals[rt[c]] = acc * rinv[c];
     }
-    const int lo = gi[4 + c] + kCutThreads, hi = gi[5 + c];
+    const int lo = cr[c] + kCutThreads, hi = cr[c + 1];
     for (int t = lo + threadIdx.x; t < hi; t += kCutThreads) {
       const Refs8 rr = srefs[t];
       T nb[8];
