@@ -62,9 +62,12 @@ struct CutPlan {
 
 // LDS layout of one cut group: values (closure, external, one zero slot),
 // right-hand sides, inverse diagonals, 8 off-diagonal coefficients per node,
-// 8 neighbour slots (int16) per node; every block 16-byte aligned.
+// 8 neighbour slots (int16) per node, and 64 bytes per lane of a wave where
+// lanes with no node store what they loaded (so that the staging stores
+// need no branch: 8 words of one lane lie 64 words apart); every block
+// 16-byte aligned.
 struct CutLds {
-  int vals, b, invd, coef, refs, total;
+  int vals, b, invd, coef, refs, dump, total;
 };
 __host__ __device__ inline CutLds cut_lds_layout(int cl, int ext, int ts) {
   auto a16 = [](int v) { return (v + 15) & ~15; };
@@ -74,7 +77,8 @@ __host__ __device__ inline CutLds cut_lds_layout(int cl, int ext, int ts) {
   L.invd = L.b + a16(cl * ts);
   L.coef = L.invd + a16(cl * ts);
   L.refs = L.coef + a16(8 * cl * ts);
-  L.total = L.refs + 16 * cl;
+  L.dump = L.refs + 16 * cl;
+  L.total = L.dump + 64 * 64;
   return L;
 }
 

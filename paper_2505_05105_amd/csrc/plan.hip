@@ -232,6 +232,9 @@ int build_plans(mgfem_ctx* c) {
     if ((rc = upload(c, &L.cp.cl_q, gb.q))) return rc;
     if ((rc = upload(c, &L.cp.cl_own, gb.own))) return rc;
     if ((rc = upload(c, &L.cp.cl_nbr, gb.nbr))) return rc;
+    // entry 0 is read (and not used) by lanes beyond a group's count, so a
+    // level whose groups have no external node still gets one (a node index)
+    if (gb.ext.empty()) gb.ext.push_back(0);
     if ((rc = upload(c, &L.cp.ext_src, gb.ext))) return rc;
     MGFEM_HIP_TRY(ctx_alloc_t(c, &L.cp.cl_coef, 9 * std::max<size_t>(1, gb.node.size())));
     if (mixed) MGFEM_HIP_TRY(ctx_alloc_t(c, &L.cp.cl_coef32, 9 * std::max<size_t>(1, gb.node.size())));

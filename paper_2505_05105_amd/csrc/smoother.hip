@@ -491,27 +491,61 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
     sb[t] = bv;
     sinv[t] = cf[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) scoef[8 * t + e] = cf[e];
+    for (int e = 0; e < 8; ++e) scoef[e * cl_cnt + t] = cf[e];
     srefs[t] = rr;
     return k;
   };
-  // the first KW closure nodes of this thread keep their grid index and
-  // ownership in registers for the write-back at the end
+  // The first closure node and the first external node of this thread are
+  // staged in two rounds of global loads: every index and row load, then
+  // every value load they point at, then the LDS stores.  The stores do not
+  // branch (a lane beyond the counts loads entry 0 of the arrays, which a
+  // level with groups always has, and stores into its own slot of the dump
+  // area), since a store under a branch lets the compiler move the loads
+  // that feed it under the branch too, one node after the other.  The second
+  // closure node of each thread (groups of more than 256 nodes, a uniform
+  // test) and nodes beyond take the same path and the loops after.  The
+  // first KW nodes keep their grid index and ownership in registers for the
+  // write-back at the end.  Coefficients lie in LDS plane by plane
+  // (coefficient e of node t at e * cl_cnt + t), so that consecutive lanes
+  // store and load consecutive words.
   constexpr int KW = 2;
-  int64_t wk[KW];
-  uint8_t wo[KW];
-#pragma unroll
-  for (int u = 0; u < KW; ++u) {
+  int64_t wk[KW] = {0, 0};
+  uint8_t wo[KW] = {0, 0};
+  const int lane = threadIdx.x & 63;
+  T* dump = reinterpret_cast<T*>(smem + lay.dump);
+  auto stage2 = [&](int u, bool with_ext) {
     const int t = threadIdx.x + u * kCutThreads;
-    wo[u] = 0;
-    wk[u] = 0;
-    if (t < cl_cnt) {
-      wo[u] = a.cl_own[cl_off + t];
-      wk[u] = stage(t);
-    }
-  }
+    const bool in = t < cl_cnt;
+    const int e = in ? cl_off + t : 0;
+    const int64_t k = a.cl_node[e];
+    const int q = a.cl_q[e];
+    const uint8_t own = a.cl_own[e];
+    const T* cg = a.cl_coef + 9 * (int64_t)e;
+    T cf[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) cf[c] = cg[c];
+    const Refs8 rr = reinterpret_cast<const Refs8*>(a.cl_nbr)[e];
+    const int te = threadIdx.x;
+    const int src = with_ext ? a.ext_src[te < ext_cnt ? ext_off + te : 0] : 0;
+    const T v = a.snap[q];
+    const T bv = a.b[k];
+    const T ev = with_ext ? *(src >= 0 ? a.x + src : a.snap + (-(1 + src))) : T(0);
+    *(in ? vals + t : dump + lane) = v;
+    *(in ? sb + t : dump + lane) = bv;
+    *(in ? sinv + t : dump + lane) = cf[8];
+    T* pc = in ? scoef + t : dump + lane;
+    const int cs = in ? cl_cnt : 64;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) pc[c * cs] = cf[c];
+    *(in ? srefs + t : reinterpret_cast<Refs8*>(dump) + lane) = rr;
+    if (with_ext) *(te <= ext_cnt ? vals + cl_cnt + te : dump + lane) = te < ext_cnt ? ev : T(0);
+    wk[u] = k;
+    wo[u] = in ? own : 0;
+  };
+  stage2(0, true);
+  if (cl_cnt > kCutThreads) stage2(1, false);
   for (int t = threadIdx.x + KW * kCutThreads; t < cl_cnt; t += kCutThreads) stage(t);
-  for (int t = threadIdx.x; t <= ext_cnt; t += kCutThreads) {
+  for (int t = threadIdx.x + kCutThreads; t <= ext_cnt; t += kCutThreads) {
     T v = T(0);
     if (t < ext_cnt) {
       const int src = a.ext_src[ext_off + t];
@@ -534,7 +568,7 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
     rb[c] = sb[tt];
     rinv[c] = sinv[tt];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) rcf[c][e] = scoef[8 * tt + e];
+    for (int e = 0; e < 8; ++e) rcf[c][e] = scoef[e * cl_cnt + tt];
   }
   // one colour phase; called with a literal colour so that the register
   // arrays above are indexed by constants (a run-time index would move them
@@ -557,7 +591,7 @@ __device__ void cut_group(const CutArgs<T>& a, const int g, unsigned char* smem)
       for (int e = 0; e < 8; ++e) nb[e] = vals[rr.r[e]];
       T acc = sb[t];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) acc -= scoef[8 * t + e] * nb[e];
+      for (int e = 0; e < 8; ++e) acc -= scoef[e * cl_cnt + t] * nb[e];
       vals[t] = acc * sinv[t];
     }
     __syncthreads();
