@@ -167,10 +167,26 @@ __global__ void k_dot_partial(const double* __restrict__ a, const double* __rest
 __global__ __launch_bounds__(1024) void k_reduce_final(const double* __restrict__ part, int nb,
                                                       double* __restrict__ out, double* host_out, double* seq) {
   __shared__ double smax[16], ssum[16];
+  // pairs in chunks of 8 per thread, the loads of a chunk issued together (a
+  // lane beyond nb reads pair 0 and drops it: loads under a branch would
+  // wait for one another)
+  constexpr int U = 8;
   double mx = 0.0, sm = 0.0;
-  for (int t = threadIdx.x; t < nb; t += blockDim.x) {
-    mx = nanmax(mx, part[2 * t]);
-    sm += part[2 * t + 1];
+  for (int base = 0; base < nb; base += U * 1024) {
+    double lm[U], ls[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = base + threadIdx.x + u * 1024;
+      const int tt = t < nb ? t : 0;
+      lm[u] = part[2 * tt];
+      ls[u] = part[2 * tt + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = base + (int)threadIdx.x + u * 1024 < nb;
+      mx = nanmax(mx, in ? lm[u] : 0.0);
+      sm += in ? ls[u] : 0.0;
+    }
   }
   for (int o = 32; o > 0; o >>= 1) {
     mx = nanmax(mx, __shfl_xor(mx, o));

@@ -140,33 +140,53 @@ __device__ inline T gs_value(const T* __restrict__ A, int64_t n, int64_t k, bool
 //           separate prolongation pass).
 //  norm:    before the first phase, the residual of the incoming iterate on
 //           the core is reduced into per-tile partials (max |r|, sum r^2).
-// final reduction of (max, sum) pairs in a fixed order
-__global__ __launch_bounds__(256) void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out, double* host_out,
+// final reduction of (max, sum) pairs in a fixed order: each of the 1024
+// threads takes the pairs in chunks of four, the loads of a chunk issued
+// together (a lane beyond nb reads pair 0 and drops it: loads under a branch
+// would wait for one another), then a wave reduction and the 16 waves in
+// order
+__global__ __launch_bounds__(1024) void k_reduce_pairs(const double* __restrict__ part, int nb, double* __restrict__ out, double* host_out,
                                double* seq) {
-  __shared__ double smx[256], ssm[256];
+  __shared__ double smx[16], ssm[16];
+  constexpr int U = 4;
   double mx = 0.0, sm = 0.0;
-  for (int q = threadIdx.x; q < nb; q += 256) {
-    mx = nanmax2(mx, part[2 * q]);
-    sm += part[2 * q + 1];
-  }
-  smx[threadIdx.x] = mx;
-  ssm[threadIdx.x] = sm;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      smx[threadIdx.x] = nanmax2(smx[threadIdx.x], smx[threadIdx.x + w]);
-      ssm[threadIdx.x] += ssm[threadIdx.x + w];
+  for (int base = 0; base < nb; base += U * 1024) {
+    double lm[U], ls[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = base + threadIdx.x + u * 1024;
+      const int qq = q < nb ? q : 0;
+      lm[u] = part[2 * qq];
+      ls[u] = part[2 * qq + 1];
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = base + (int)threadIdx.x + u * 1024 < nb;
+      mx = nanmax2(mx, in ? lm[u] : 0.0);
+      sm += in ? ls[u] : 0.0;
+    }
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = nanmax2(mx, __shfl_xor(mx, o));
+    sm += __shfl_xor(sm, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smx[threadIdx.x >> 6] = mx;
+    ssm[threadIdx.x >> 6] = sm;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    out[0] = smx[0];
-    out[1] = ssm[0];
+    for (int w = 1; w < 16; ++w) {
+      mx = nanmax2(mx, smx[w]);
+      sm += ssm[w];
+    }
+    out[0] = mx;
+    out[1] = sm;
     const double q = seq[0] + 1.0;  // counted on the device (graph replays)
     seq[0] = q;
     double* rec = host_out + 4 * (int)((long long)q % kRedSlots);
-    rec[0] = smx[0];  // straight to pinned host memory; the sequence number goes last
-    rec[1] = ssm[0];
+    rec[0] = mx;  // straight to pinned host memory; the sequence number goes last
+    rec[1] = sm;
     __threadfence_system();
     rec[2] = q;
     __threadfence_system();
@@ -1398,7 +1418,7 @@ void launch_sweep(mgfem_ctx* c, int l, bool reverse, bool norm, bool prolong_fro
   }
   if (norm) {
     c->red_seq += 1.0;
-    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, c->s, (const double*)c->sweep_part, a.ntiles,
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(1024), 0, c->s, (const double*)c->sweep_part, a.ntiles,
                        c->red_out, c->red_host, c->red_seq_dev);
   }
   L.cur = 1 - L.cur;
