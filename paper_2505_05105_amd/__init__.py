@@ -216,12 +216,21 @@ class Solver:
             pass
 
 
+def _float64_solver(solver):
+    if solver.params.precision != PREC_FP64:
+        raise ValueError("the backward pass is the transposed float64 k-cycle map, the exact gradient of a "
+                         "float64 solve only: use a float64 solver (or Solver.adjoint directly)")
+
+
 class GhostFEMSolve(torch.autograd.Function):
-    """u = B_k (M f + G g) with k cycles; backward applies the exact transposed
-    k-cycle map: dL/df = M lam, dL/dg = G^T lam, lam = B_k^T dL/du."""
+    """u = B_k (M f + G g) with k float64 cycles; backward applies the exact
+    transposed k-cycle map: dL/df = M lam, dL/dg = G^T lam, lam = B_k^T dL/du
+    (the gradient of the map the forward ran, not of the converged discrete
+    solution).  Needs a float64 solver."""
 
     @staticmethod
     def forward(ctx, f, g, solver, tol=1e-10, max_cycles=50):
+        _float64_solver(solver)
         u, hist = solver.solve(f.detach(), g.detach(), tol=tol, max_cycles=max_cycles)
         ctx.solver = solver
         ctx.cycles = len(hist) - 1
@@ -234,12 +243,14 @@ class GhostFEMSolve(torch.autograd.Function):
 
 
 class GhostFEMSolveMixed(torch.autograd.Function):
-    """Mixed boundaries: u = B_k (M f + G g_D + GN g_N) with k cycles on a
-    solver set up with an indicator; backward gives dL/df = M lam,
-    dL/dg_D = G^T lam and dL/dg_N = GN^T lam (mgfem_adjoint_neumann)."""
+    """Mixed boundaries: u = B_k (M f + G g_D + GN g_N) with k float64 cycles
+    on a solver set up with an indicator; backward gives dL/df = M lam,
+    dL/dg_D = G^T lam and dL/dg_N = GN^T lam (mgfem_adjoint_neumann).  Needs
+    a float64 solver."""
 
     @staticmethod
     def forward(ctx, f, gD, gN, solver, tol=1e-10, max_cycles=50):
+        _float64_solver(solver)
         u, hist = solver.solve(f.detach(), gD.detach(), tol=tol, max_cycles=max_cycles, gN=gN.detach())
         ctx.solver = solver
         ctx.cycles = len(hist) - 1

@@ -255,6 +255,11 @@ def test_autograd_function_matches_finite_differences():
             J0 = J_of(f.detach(), g.detach())[1]
             assert float(grad @ dvt) == pytest.approx(fd, rel=1e-6, abs=50 * 2.2e-16 * abs(J0) / eps)
     del M
+    # the backward pass is the transposed float64 cycle map: a mixed-precision
+    # forward would not be its transpose, so such a solver is refused
+    sm = mg.Solver(p.psi, N, precision=mg.PREC_MIXED)
+    with pytest.raises(ValueError):
+        mg.GhostFEMSolve.apply(f, g, sm, -1.0, k)
 
 
 def test_stabilisation_rules():
