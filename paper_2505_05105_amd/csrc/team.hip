@@ -18,6 +18,7 @@
 // iterate from buffer 0, where its coarse map writes it.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "mgfem_internal.h"
@@ -244,9 +245,37 @@ int team_solve(mgfem_ctx* b, const double* const* f, const double* const* g, dou
   int m = 0;
   bool changed = next.size() != active.size();
   active.swap(next);
+  // Float32 cycles of each step: inner_cycles, or fewer when every problem
+  // still iterating would run fewer in its own mixed-precision solve, by the
+  // single-problem rule: a problem whose last factor, applied once more,
+  // still leaves it 4x above its target, and any problem in its first two
+  // steps, needs the full count; any other needs the number of its last
+  // step's factors per float32 cycle that brings its residual to the target.
+  // All problems of a step share one count (their cycles share launches).
+  const int K = b->p.inner_cycles;
+  const char* fi_env = std::getenv("MGFEM_FIXED_INNER");
+  const bool adapt = K > 1 && rel_tol > 0.0 && !(fi_env && fi_env[0] && fi_env[0] != '0');
+  std::vector<int> step_k;  // float32 cycles of each step
+  auto need = [&](int p, int j) -> int {  // step j = m + 1 of problem p
+    const double* h = hist.data() + (size_t)p * H;
+    if (j < 3) return K;
+    const double rq = h[j - 3] > 0.0 ? h[j - 2] / h[j - 3] : 1.0;
+    if (h[j - 2] * rq > 4.0 * rel_tol * bnorm[p]) return K;
+    const double r = h[j - 1], rp = h[j - 2];
+    const int kp = step_k[j - 2];
+    if (!(r > 0.0) || !(rp > r) || kp < 1) return K;
+    const double rho = std::pow(r / rp, 1.0 / kp);
+    const double n = std::log(rel_tol * bnorm[p] / r) / std::log(rho);
+    if (!std::isfinite(n)) return K;
+    return std::max(1, std::min(K, (int)std::ceil(n)));
+  };
   while (!active.empty() && m < max_cycles) {
     if (changed && (rc = team_lists(b, T, active, false))) return rc;
-    for (int q = 0; q < b->p.inner_cycles; ++q) team_level(b, T, 0, par);
+    int kstep = adapt ? 1 : K;
+    if (adapt)
+      for (int p : active) kstep = std::max(kstep, need(p, m + 1));
+    step_k.push_back(kstep);
+    for (int q = 0; q < kstep; ++q) team_level(b, T, 0, par);
     const int ce = par[0];
     launch_l0(b, T, kTeamOuter, upar, ce);
     upar ^= 1;

@@ -151,12 +151,13 @@ def test_tiled_batch_path_equals_single_mixed_solves(inner):
         um, hm = s.solve(p.f, p.g, tol=-1.0, max_cycles=3)
         assert np.array_equal(h, hm), (p.N, h, hm)
         assert torch.equal(u, um), p.N
-    us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
+    # both forms with every step at the full count (each shortens its last
+    # steps by its own rule otherwise: the batch by the problems' largest need)
+    with _env(MGFEM_FIXED_INNER="1"):
+        us, hists = bs.solve([p.f for p in probs], [p.g for p in probs], tol=1e-10, max_cycles=80)
     assert bs.last_status == 0
     for p, u, h in zip(probs, us, hists):
         s = _single_mixed(mg, p, inner_cycles=inner)
-        # the batch runs every step with inner_cycles float32 cycles; the
-        # single solver would shorten its last step
         with _env(MGFEM_FIXED_INNER="1"):
             um, hm = s.solve(p.f, p.g, tol=1e-10, max_cycles=80)
         assert len(h) == len(hm) and torch.equal(u, um), p.N
