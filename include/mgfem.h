@@ -366,8 +366,11 @@ const char* mgfem_last_error(mgfem_handle h);
  * whose workgroups take whole problems from a queue, with one of four
  * footprint widths.  Parameters are shared by all problems (both paths run
  * params.inner_cycles float32 cycles per float64 step, as mgfem_solve in
- * mixed precision); the whole boundary is Dirichlet.  MGFEM_BATCH_PATH=tiled
- * or =persistent at set-up fixes the choice.
+ * mixed precision; with rel_tol > 0 the tiled path runs a step with fewer
+ * when no problem still iterating needs more by mgfem_solve's rule, and
+ * MGFEM_FIXED_INNER=1 keeps the full count); the whole boundary is
+ * Dirichlet.  MGFEM_BATCH_PATH=tiled or =persistent at set-up fixes the
+ * choice.
  *  psi_dev[i] : device (N[i]+1)^2 float64.  N[i] as in mgfem_setup.
  */
 int mgfem_setup_batched(int32_t count, const double* const* psi_dev, const int32_t* N,
