@@ -56,3 +56,12 @@ def test_host_only_calls(lib):
     rc = _lib.lib().mgfem_setup(ctypes.c_void_p(16), 96, ctypes.byref(p), None, ctypes.byref(h))
     assert rc == _lib.ERR_INVALID_ARG
     assert _lib.lib().mgfem_level_n(None, 0) == -1
+    # history queries reject a null handle and a negative capacity
+    cnt = ctypes.c_int32(7)
+    assert _lib.lib().mgfem_step_cycles(None, None, 0, ctypes.byref(cnt)) == _lib.ERR_INVALID_ARG
+    assert _lib.lib().mgfem_residual_l2(None, None, 0, ctypes.byref(cnt)) == _lib.ERR_INVALID_ARG
+    # inner_cycles outside 1..16 is rejected for mixed precision, before any device work
+    for k in (0, 17):
+        bad = _lib.default_params(precision=_lib.PREC_MIXED, inner_cycles=k)
+        rc = _lib.lib().mgfem_setup(ctypes.c_void_p(16), 64, ctypes.byref(bad), None, ctypes.byref(h))
+        assert rc == _lib.ERR_INVALID_ARG and "inner_cycles" in _lib.last_error(None)

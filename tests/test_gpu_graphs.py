@@ -173,6 +173,10 @@ def test_mixed_steps_shortened_from_the_history():
         assert scf == [3] * (len(hf) - 1)
         assert sum(sc) <= sum(scf), (name, sc, scf)
         print(f"{name} N={N}: float32 cycles per step {sc} (fixed: {scf})")
+    # a float64 solve runs one cycle per iteration
+    s64 = _solver(mg, p, N, True)
+    u, h = s64.solve(p.f, p.g, tol=1e-10)
+    assert list(s64.step_cycles()) == [1] * (len(h) - 1)
 
 
 def test_list_smoother_without_group_plans():
