@@ -423,8 +423,11 @@ __device__ void sweep_tile(const SweepArgs<T>& a, const int t) {
 // of one level share an XCD's L2.
 __device__ inline int xcd_item(int per) { return (blockIdx.x & 7) * per + (blockIdx.x >> 3); }
 
+// The float 64 x 16 instance is held to 64 registers, so that four of its
+// workgroups share a CU and the N = 2048 level's tiles start in one round
+// (the float64 instance would spill at that bound).
 template <class T, int TW, int TH, int BS>
-__global__ __launch_bounds__(BS) void k_sweep(SweepArgs<T> a) {
+__global__ __launch_bounds__(BS, (sizeof(T) == 4 && TW == 64 && TH == 16) ? 8 : 1) void k_sweep(SweepArgs<T> a) {
   const int t = xcd_item(a.per);
   if (t >= a.ntiles) return;  // uniform for the whole block, before any barrier
   sweep_tile<T, TW, TH, BS>(a, t);
