@@ -85,24 +85,29 @@ __device__ inline void block_pair(double mx, double sm, double* __restrict__ par
 
 // A block of the box kernels owns 256 x 4 nodes; the values its stencils read
 // are staged in LDS with a halo of one (zero off the grid), every global load
-// of the staging issued before the first is used.
+// of the staging issued before the first is used: none sits under a branch
+// (a node off the grid loads a clamped on-grid node and stores zero; the
+// LDS area is padded to whole rounds of the block, kSNP), since a load under
+// a branch waits for the ones before it.
 constexpr int kBX = 256, kBY = kNodesPerThread, kSW = kBX + 2, kSH = kBY + 2, kSN = kSW * kSH;
+constexpr int kSNP = (kSN + 255) / 256 * 256;
 
 template <class Load>
 __device__ inline void stage_box(double* __restrict__ sv, int bi, int bj, int N, int s, Load load) {
-  constexpr int NU = (kSN + 255) / 256;
+  constexpr int NU = kSNP / 256;
   double r[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int q = min(threadIdx.x + u * 256, kSN - 1);
+    const int gi = min(max(bi - 1 + q % kSW, 0), N), gj = min(max(bj - 1 + q / kSW, 0), N);
+    r[u] = load(gi + (int64_t)gj * s);
+  }
 #pragma unroll
   for (int u = 0; u < NU; ++u) {
     const int q = threadIdx.x + u * 256;
     const int gi = bi - 1 + q % kSW, gj = bj - 1 + q / kSW;
     const bool in = q < kSN && gi >= 0 && gj >= 0 && gi <= N && gj <= N;
-    r[u] = in ? load(gi + (int64_t)gj * s) : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < NU; ++u) {
-    const int q = threadIdx.x + u * 256;
-    if (q < kSN) sv[q] = r[u];
+    sv[q] = in ? r[u] : 0.0;
   }
   __syncthreads();
 }
@@ -131,7 +136,7 @@ __device__ inline double box_row(const double* __restrict__ A, int64_t n, int64_
 __global__ __launch_bounds__(256) void k_resnorm_partial(LevelView<double> v, const double* __restrict__ F,
                                                          double* r_out, int i0, int j0, int ni, int nj,
                                                          double* __restrict__ part) {
-  __shared__ double sv[kSN];
+  __shared__ double sv[kSNP];
   const int bi = i0 + blockIdx.x * kBX, bj = j0 + blockIdx.y * kBY;
   const double* x = v.x;
   stage_box(sv, bi, bj, v.N, v.s, [&](int64_t k) { return x[k]; });
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ M, const
                                              const double* __restrict__ gn, double* __restrict__ F, int N,
                                              double hh36, int i0, int j0, int ni, int nj,
                                              double* __restrict__ part) {
-  __shared__ double sv[kSN];
+  __shared__ double sv[kSNP];
   const int s = N + 1;
   const int64_t n = (int64_t)s * s;
   const int bi = i0 + blockIdx.x * kBX, bj = j0 + blockIdx.y * kBY;
@@ -355,7 +360,7 @@ __global__ __launch_bounds__(256) void k_rhs(const double* __restrict__ M, const
 __global__ __launch_bounds__(256) void k_mass_grid(const double* __restrict__ M, const uint8_t* __restrict__ fl,
                                                    const double* __restrict__ x, double* __restrict__ y, int N,
                                                    double hh36, int i0, int j0, int i1, int j1) {
-  __shared__ double sv[kSN];
+  __shared__ double sv[kSNP];
   const int s = N + 1;
   const int64_t n = (int64_t)s * s;
   const int bi = blockIdx.x * kBX, bj = blockIdx.y * kBY;
@@ -388,7 +393,7 @@ __global__ __launch_bounds__(256) void k_outer(LevelView<double> v, const double
                                                double* __restrict__ u_out, float* __restrict__ r32,
                                                float* __restrict__ z32, int i0, int j0, int ni, int nj,
                                                double* __restrict__ part) {
-  __shared__ double sv[kSN];
+  __shared__ double sv[kSNP];
   const int bi = i0 + blockIdx.x * kBX, bj = j0 + blockIdx.y * kBY;
   if (e) stage_box(sv, bi, bj, v.N, v.s, [&](int64_t k) { return u[k] + (double)e[k]; });
   else stage_box(sv, bi, bj, v.N, v.s, [&](int64_t k) { return u[k]; });
@@ -406,6 +411,90 @@ __global__ __launch_bounds__(256) void k_outer(LevelView<double> v, const double
     const double ax = (f & kFlagStored) ? box_row(v.A, v.n, k, sv, q)
                                         : 8.0 / 3.0 * uk - box_neighbours(sv, q) * (1.0 / 3.0);
     const double r = F[k] - ax;
+    if (u_out) u_out[k] = uk;
+    r32[k] = (float)r;
+    z32[k] = 0.0f;
+    mx = nanmax(mx, fabs(r));
+    sm += r * r;
+  }
+  block_pair(mx, sm, part);
+}
+
+// The same outer step over the level's sweep tiles that hold an active node
+// (TW x TH cores, in the tile list of the sweeps) instead of the whole box
+// of active nodes: blocks of the box with no active node cost no loads.
+// Each block stages its core plus a ring of one (u + e, zero off the grid)
+// with every load issued before the first is used; the arithmetic of a node
+// is that of k_outer, operation for operation.  Partials in tile-list order.
+template <int TW, int TH, bool E>
+__global__ __launch_bounds__(256) void k_outer_tiles(LevelView<double> v, const int* __restrict__ tiles, int ntx,
+                                                     int i0, int j0, int i1, int j1, const double* __restrict__ F,
+                                                     const double* __restrict__ u, const float* __restrict__ e,
+                                                     double* __restrict__ u_out, float* __restrict__ r32,
+                                                     float* __restrict__ z32, double* __restrict__ part) {
+  constexpr int SW = TW + 2, SN = SW * (TH + 2), NU = (SN + 255) / 256, NC = TW * TH / 256;
+  __shared__ double sv[NU * 256];  // the region, padded to whole rounds of the block
+  const int tile = tiles[blockIdx.x];
+  const int bi = i0 + (tile % ntx) * TW, bj = j0 + (tile / ntx) * TH;
+  // Every load of the block issued before any is used, none under a branch
+  // (a node off the grid or beyond the box reads a clamped on-grid node and
+  // drops it): the staged u + e, then the flags and F of this thread's core
+  // nodes.
+  double ru[NU];
+  float re[NU];
+#pragma unroll
+  for (int w = 0; w < NU; ++w) {
+    const int q = min(threadIdx.x + w * 256, SN - 1);
+    const int gi = min(max(bi - 1 + q % SW, 0), v.N), gj = min(max(bj - 1 + q / SW, 0), v.N);
+    const int64_t k = gi + (int64_t)gj * v.s;
+    ru[w] = u[k];
+    re[w] = E ? e[k] : 0.0f;
+  }
+  uint8_t fk[NC];
+  double Fk[NC];
+#pragma unroll
+  for (int w = 0; w < NC; ++w) {
+    const int c = threadIdx.x + w * 256;
+    const int i = bi + c % TW, j = bj + c / TW;
+    const int64_t k = min(i, v.N) + (int64_t)min(j, v.N) * v.s;
+    fk[w] = v.fl[k] & ((i <= i1 && j <= j1) ? 0xff : 0);
+    Fk[w] = F[k];
+  }
+#pragma unroll
+  for (int w = 0; w < NU; ++w) {
+    const int q = threadIdx.x + w * 256;
+    const int gi = bi - 1 + q % SW, gj = bj - 1 + q / SW;
+    const bool in = gi >= 0 && gj >= 0 && gi <= v.N && gj <= v.N;
+    sv[q] = in ? (E ? ru[w] + (double)re[w] : ru[w]) : 0.0;
+  }
+  __syncthreads();
+  double mx = 0.0, sm = 0.0;
+#pragma unroll
+  for (int w = 0; w < NC; ++w) {
+    const int c = threadIdx.x + w * 256;
+    const uint8_t f = fk[w];
+    if (!(f & kFlagActive)) continue;
+    const int64_t k = (bi + c % TW) + (int64_t)(bj + c / TW) * v.s;
+    const int q = (c % TW + 1) + (c / TW + 1) * SW;
+    const double uk = sv[q];
+    double ax;
+    if (f & kFlagStored) {
+      const int64_t n = v.n;
+      ax = v.A[4 * n + k] * sv[q];
+      ax += v.A[k] * sv[q - SW - 1];
+      ax += v.A[n + k] * sv[q - SW];
+      ax += v.A[2 * n + k] * sv[q - SW + 1];
+      ax += v.A[3 * n + k] * sv[q - 1];
+      ax += v.A[5 * n + k] * sv[q + 1];
+      ax += v.A[6 * n + k] * sv[q + SW - 1];
+      ax += v.A[7 * n + k] * sv[q + SW];
+      ax += v.A[8 * n + k] * sv[q + SW + 1];
+    } else {
+      const double nb = (sv[q - SW - 1] + sv[q - SW] + sv[q - SW + 1]) + (sv[q - 1] + sv[q + 1]) +
+                        (sv[q + SW - 1] + sv[q + SW] + sv[q + SW + 1]);
+      ax = 8.0 / 3.0 * uk - nb * (1.0 / 3.0);
+    }
+    const double r = Fk[w] - ax;
     if (u_out) u_out[k] = uk;
     r32[k] = (float)r;
     z32[k] = 0.0f;
@@ -455,6 +544,23 @@ void launch_rhs(mgfem_ctx* c, const double* f, const double* g, const double* gN
 void launch_outer(mgfem_ctx* c, const double* u, const float* e, double* u_out, float* r32, float* z32) {
   Level& L = c->lv[0];
   LevelView<double> v{L.A, L.flags, nullptr, nullptr, nullptr, L.N, L.stride, L.n};
+  if (L.tiles && L.ntiles > 0) {
+    // over the active sweep tiles of level 0, in their shape
+    const int shape = sweep_shape(c, 0);
+    const int TW = shape == kShapeSmall ? 16 : 64, TH = shape == kShapeFinest ? 32 : 16;
+    const int ntx = (L.bbox[1] - L.bbox[0] + TW) / TW;
+    auto go = [&](auto kern) {
+      hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(256), 0, c->s, v, (const int*)L.tiles, ntx, L.bbox[0],
+                         L.bbox[2], L.bbox[1], L.bbox[3], (const double*)L.b, u, e, u_out, r32, z32, c->sweep_part);
+    };
+    if (shape == kShapeFinest) e ? go(k_outer_tiles<64, 32, true>) : go(k_outer_tiles<64, 32, false>);
+    else if (shape == kShapeLarge) e ? go(k_outer_tiles<64, 16, true>) : go(k_outer_tiles<64, 16, false>);
+    else e ? go(k_outer_tiles<16, 16, true>) : go(k_outer_tiles<16, 16, false>);
+    c->red_seq += 1.0;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(1024), 0, c->s, (const double*)c->sweep_part, L.ntiles,
+                       c->red_out, c->red_host, c->red_seq_dev);
+    return;
+  }
   const int ni = L.bbox[1] - L.bbox[0] + 1, nj = L.bbox[3] - L.bbox[2] + 1;
   const dim3 grid((unsigned)std::max(1, (ni + 255) / 256), (unsigned)std::max(1, (nj + 3) / 4));
   const int nb = (int)(grid.x * grid.y);
@@ -661,7 +767,7 @@ __global__ __launch_bounds__(256) void k_team_cut_rows(const TeamL0* __restrict_
 
 __global__ __launch_bounds__(256) void k_team_rhs(const TeamL0* __restrict__ tab, const int2* __restrict__ work,
                                                   int nwork) {
-  __shared__ double sv[kSN];
+  __shared__ double sv[kSNP];
   if ((int)blockIdx.x >= nwork) return;
   const int2 w = work[blockIdx.x];
   const TeamL0& e = tab[w.x];
@@ -694,7 +800,7 @@ __global__ __launch_bounds__(256) void k_team_rhs(const TeamL0* __restrict__ tab
 // nodes); else u_new = U[upar] + E[epar] into U[1 - upar]
 __global__ __launch_bounds__(256) void k_team_outer(const TeamL0* __restrict__ tab, const int2* __restrict__ work,
                                                     int nwork, int upar, int epar, int first) {
-  __shared__ double sv[kSN];
+  __shared__ double sv[kSNP];
   if ((int)blockIdx.x >= nwork) return;
   const int2 w = work[blockIdx.x];
   const TeamL0& e = tab[w.x];
