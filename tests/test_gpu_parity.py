@@ -174,6 +174,35 @@ def test_warm_start_continues():
     assert rel_max(u2.cpu().numpy(), ref.u) < 1e-12
 
 
+@pytest.mark.parametrize("N", [256, 1024])
+def test_mixed_outer_residual_matches_oracle_operator(N):
+    """The float64 outer step of the mixed solve (over the level's sweep
+    tiles: 16 x 16 at N = 256, 64 x 16 at N = 1024) reports the norms of
+    F - A u for the iterate it returns: recomputed on the host from the
+    library's own stencil planes (the oracle's agree with them only to
+    ~1e-13, more than a small residual can tell apart) and the oracle's
+    right-hand side after one and two steps, the max and l2 norms agree to
+    the rounding of A u."""
+    mg = _gpu()
+    p, d, H = oracle_for("flower", N)
+    F = d.rhs(p.f, p.g)
+    s = mg.Solver(p.psi, N, precision=mg.PREC_MIXED)
+    A = s.export(mg._lib.EXPORT_A, 0).cpu().numpy().reshape(9, N + 1, N + 1)
+    for k in (1, 2):
+        u, hist = s.solve(p.f, p.g, tol=-1.0, max_cycles=k)
+        U = np.pad(u.cpu().numpy().reshape(N + 1, N + 1), 1)
+        Au = np.zeros((N + 1, N + 1))
+        for q in range(9):
+            di, dj = q % 3 - 1, q // 3 - 1
+            Au += A[q] * U[1 + dj:N + 2 + dj, 1 + di:N + 2 + di]
+        r = (F - Au.reshape(-1)) * d.active
+        floor = 64 * 2.2e-16 * 6 * np.abs(u.cpu().numpy()).max()
+        assert hist[-1] > 1e3 * floor
+        assert abs(np.abs(r).max() - hist[-1]) <= 1e-6 * hist[-1] + floor
+        l2 = s.residual_l2()[-1]
+        assert abs(np.linalg.norm(r) - l2) <= 1e-6 * l2 + floor * np.sqrt(d.n)
+
+
 def test_mixed_precision_reaches_fp64_tolerance():
     """FP32 cycles inside FP64 defect correction reach the FP64 residual
     tolerance; the solution error against the FP64 oracle is then of the size
