@@ -175,7 +175,7 @@ def test_warm_start_continues():
 
 
 @pytest.mark.parametrize("N", [256, 1024])
-def test_mixed_outer_residual_matches_oracle_operator(N):
+def test_mixed_outer_residual_matches_host_recomputation(N):
     """The float64 outer step of the mixed solve (over the level's sweep
     tiles: 16 x 16 at N = 256, 64 x 16 at N = 1024) reports the norms of
     F - A u for the iterate it returns: recomputed on the host from the
